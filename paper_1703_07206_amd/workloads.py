@@ -1,0 +1,196 @@
+"""Seeded synthetic inputs for the SGML solver.
+
+This module holds no part of the solver's arithmetic: it only draws the
+right-hand sides, coefficients and boundary values of the problems below,
+with numpy's PCG64 (``numpy.random.default_rng(seed)``), in FP64, on the
+host.  The same arrays feed the GPU library and the CPU oracle.
+
+Every problem is returned in the paper's form L(u) = f with
+L = div(sigma grad) + a on [0,1]^d, N = 2^n + 1 nodes per axis, arrays
+indexed [j, i] (2D) or [k, j, i] (3D) with i along x.  A Poisson problem
+-lap(u) = f is therefore handed over with source -f.
+
+Workloads (shaped like the paper's 2D Poisson and 3D heterogeneous
+Helmholtz-Poisson examples):
+
+``poisson2d_sine``   129^2, 5-point, Dirichlet 0, f = 2 pi^2 sin sin + 0.1 U(-1,1)
+``poisson2d_blobs``  4097^2, 5-point, Dirichlet x-walls / Neumann y-walls,
+                     64 Gaussian blobs (width 0.01-0.05, amplitude U(-1,1))
+``helmholtz3d_spheres`` 257^3, radial 27-point, eps = 1 with 32 spheres of
+                     eps in [2, 80], a = -0.5, f = 0, u = -1 / +1 on z = 0 / 1
+``helmholtz3d_adjoint`` 129^3, same medium, f = U(-1,1), loss target u_t
+``poisson3d_charges``   513^3, radial 27-point, Dirichlet 0, 256 Gaussian
+                     point charges of width 2h plus 1e-3 U(-1,1) noise
+"""
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+AXIS, RADIAL = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    n: int
+    stencil: int
+    faces: str            # 'D'/'N' for x-, x+, y-, y+, z-, z+
+    a: float
+    f: np.ndarray         # source of L(u) = f
+    sigma: Optional[np.ndarray] = None
+    G: Optional[np.ndarray] = None   # Dirichlet values (read at Dirichlet nodes only)
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self):
+        return 2 ** self.n + 1
+
+    @property
+    def nodes(self):
+        return self.N ** self.dim
+
+
+def coords(n, dim):
+    """Node coordinates x_i = i h, returned in array order (z, y, x)."""
+    N = 2 ** n + 1
+    x = np.linspace(0.0, 1.0, N)
+    return np.meshgrid(*([x] * dim), indexing="ij")
+
+
+def poisson2d_sine(n=7, seed=1, noise=0.1):
+    N = 2 ** n + 1
+    rng = np.random.default_rng(seed)
+    eta = rng.uniform(-1.0, 1.0, (N, N))
+    Y, X = coords(n, 2)
+    f = 2.0 * np.pi ** 2 * np.sin(np.pi * X) * np.sin(np.pi * Y) + noise * eta
+    return Workload("poisson2d_sine", 2, n, AXIS, "DDDD", 0.0, -f)
+
+
+def _blobs2d(n, centers, widths, amps):
+    N = 2 ** n + 1
+    x = np.linspace(0.0, 1.0, N)
+    f = np.zeros((N, N))
+    for (cx, cy), s, A in zip(centers, widths, amps):
+        gx = np.exp(-((x - cx) ** 2) / (2.0 * s * s))
+        gy = np.exp(-((x - cy) ** 2) / (2.0 * s * s))
+        f += A * np.outer(gy, gx)  # separable: exp(-|x-c|^2/2s^2) = gx(x) gy(y)
+    return f
+
+
+def poisson2d_blobs(n=12, seed=2, nblobs=64):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 1.0, (nblobs, 2))
+    s = rng.uniform(0.01, 0.05, nblobs)
+    A = rng.uniform(-1.0, 1.0, nblobs)
+    f = _blobs2d(n, c, s, A)
+    return Workload("poisson2d_blobs", 2, n, AXIS, "DDNN", 0.0, -f)
+
+
+def sphere_medium(n, seed=3, nspheres=32, eps_lo=2.0, eps_hi=80.0):
+    """eps = 1 with spheres painted in draw order (later spheres win) at the
+    nodes with |x - c| <= r."""
+    N = 2 ** n + 1
+    h = 1.0 / 2 ** n
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 1.0, (nspheres, 3))
+    r = rng.uniform(0.03, 0.15, nspheres)
+    e = rng.uniform(eps_lo, eps_hi, nspheres)
+    eps = np.ones((N, N, N))
+    for (cx, cy, cz), rr, ee in zip(c, r, e):
+        lo = [max(0, int(np.floor((q - rr) / h))) for q in (cx, cy, cz)]
+        hi = [min(N - 1, int(np.ceil((q + rr) / h))) for q in (cx, cy, cz)]
+        zi = np.arange(lo[2], hi[2] + 1)
+        yi = np.arange(lo[1], hi[1] + 1)
+        xi = np.arange(lo[0], hi[0] + 1)
+        Z, Y, X = np.meshgrid(zi * h, yi * h, xi * h, indexing="ij")
+        inside = (X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2 <= rr * rr
+        sub = eps[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+        sub[inside] = ee
+    return eps
+
+
+def capacitor_bc(n):
+    """u = -1 on the z = 0 face and +1 on the z = 1 face (their edges
+    included), 0 on the other faces."""
+    N = 2 ** n + 1
+    G = np.zeros((N, N, N))
+    G[0] = -1.0
+    G[-1] = 1.0
+    return G
+
+
+def helmholtz3d_spheres(n=8, seed=3, k=0.5):
+    N = 2 ** n + 1
+    eps = sphere_medium(n, seed)
+    return Workload("helmholtz3d_spheres", 3, n, RADIAL, "DDDDDD", -k, np.zeros((N, N, N)),
+                    sigma=eps, G=capacitor_bc(n))
+
+
+def smooth_target(n, rng, modes=8):
+    """u_t = sum_j b_j prod_i sin(m_ji pi x_i), m in {1,2,3}, b ~ U(-1,1)."""
+    m = rng.integers(1, 4, (modes, 3))
+    b = rng.uniform(-1.0, 1.0, modes)
+    Z, Y, X = coords(n, 3)
+    ut = np.zeros_like(X)
+    for (mx, my, mz), bb in zip(m, b):
+        ut += bb * np.sin(mx * np.pi * X) * np.sin(my * np.pi * Y) * np.sin(mz * np.pi * Z)
+    return ut
+
+
+def helmholtz3d_adjoint(n=7, seed_eps=3, seed=4, k=0.5, n_fd=10):
+    N = 2 ** n + 1
+    eps = sphere_medium(n, seed_eps)
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-1.0, 1.0, (N, N, N))
+    ut = smooth_target(n, rng)
+    fd_f = rng.integers(1, N - 1, (n_fd, 3))     # (k, j, i) interior picks
+    fd_eps = rng.integers(1, N - 1, (n_fd, 3))
+    return Workload("helmholtz3d_adjoint", 3, n, RADIAL, "DDDDDD", -k, f, sigma=eps,
+                    G=capacitor_bc(n), extra=dict(u_target=ut, fd_f=fd_f, fd_eps=fd_eps))
+
+
+def poisson3d_charges(n=9, seed=5, ncharges=256, noise=1e-3, cutoff=8.0):
+    """Gaussian charges of width w = 2h, evaluated exactly inside a cube of
+    half-side cutoff*w around each centre (beyond it exp(-cutoff^2/2) ~ 1e-14)."""
+    N = 2 ** n + 1
+    h = 1.0 / 2 ** n
+    w = 2.0 * h
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 1.0, (ncharges, 3))
+    A = rng.uniform(-1.0, 1.0, ncharges)
+    f = noise * rng.uniform(-1.0, 1.0, (N, N, N))
+    R = int(np.ceil(cutoff * w / h))
+    for (cx, cy, cz), amp in zip(c, A):
+        ic = [int(round(q / h)) for q in (cx, cy, cz)]
+        lo = [max(0, q - R) for q in ic]
+        hi = [min(N - 1, q + R) for q in ic]
+        gx = np.exp(-((np.arange(lo[0], hi[0] + 1) * h - cx) ** 2) / (2 * w * w))
+        gy = np.exp(-((np.arange(lo[1], hi[1] + 1) * h - cy) ** 2) / (2 * w * w))
+        gz = np.exp(-((np.arange(lo[2], hi[2] + 1) * h - cz) ** 2) / (2 * w * w))
+        f[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] += amp * np.einsum(
+            "k,j,i->kji", gz, gy, gx)
+    ut = smooth_target(n, rng)
+    return Workload("poisson3d_charges", 3, n, RADIAL, "DDDDDD", 0.0, -f,
+                    extra=dict(u_target=ut))
+
+
+def random_problem(dim, n, stencil, faces, seed, hetero=True, a=0.0, dirichlet_values=True):
+    """Small generic problem for parity tests: random source, smooth positive
+    coefficient with random contrast, random Dirichlet values."""
+    N = 2 ** n + 1
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-1.0, 1.0, (N,) * dim)
+    sigma = np.exp(rng.uniform(-1.0, 1.0, (N,) * dim)) if hetero else None
+    G = rng.uniform(-1.0, 1.0, (N,) * dim) if dirichlet_values else None
+    return Workload(f"random{dim}d", dim, n, stencil, faces, a, f, sigma=sigma, G=G)
+
+
+CONFIGS = {
+    "poisson2d_sine": poisson2d_sine,
+    "poisson2d_blobs": poisson2d_blobs,
+    "helmholtz3d_spheres": helmholtz3d_spheres,
+    "helmholtz3d_adjoint": helmholtz3d_adjoint,
+    "poisson3d_charges": poisson3d_charges,
+}

@@ -1,0 +1,476 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, invariants, special cases solved by library routines (DST-I/DCT-I,
+sparse LU, CG, a 1D tridiagonal solve), finite differences, or the
+expansion of Algorithm 3 stored in ``tests/golden``.  The per-cycle
+contraction rate is not pinned (the paper's convergence figure, Fig. 3, is
+not available) -- only reported.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import exact
+from oracle.core import AXIS, RADIAL, OracleProblem, schedule
+from paper_1703_07206_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+FACE_SETS_2D = ["DDDD", "DDNN", "NNDD", "DNDD", "NDND"]
+FACE_SETS_3D = ["DDDDDD", "DDNNNN", "NNDDNN", "DDDDNN"]
+
+
+def rel_inf(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# ----------------------------------------------------------------- schedule
+
+def _read_schedule_golden():
+    out, cur = {}, None
+    with open(os.path.join(GOLDEN, "schedule_n5.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("["):
+                cur = line.strip("[]")
+                out[cur] = []
+            else:
+                lv, ct = map(int, line.split())
+                out[cur].append((lv, ct))
+    return out
+
+
+def test_schedule_matches_algorithm3_expansion():
+    gold = _read_schedule_golden()
+    assert schedule(5, 2, 0) == gold["n_r=2"]
+    assert schedule(5, 0, 0) == gold["full"]
+
+
+def test_schedule_level_zero_work_is_constant():
+    # with n_r = 2, every n has exactly 8 level-0 relaxations per cycle
+    for n in range(2, 13):
+        s = schedule(n, 2, 0)
+        assert sum(c for lv, c in s if lv == 0) == 8
+        assert len(s) == 3 * n  # n teeth of 3 visits, minus one skipped, plus the final visit
+
+
+# ------------------------------------------------------------------ operator
+
+@pytest.mark.parametrize("dim,faces", [(2, f) for f in FACE_SETS_2D] + [(3, f) for f in FACE_SETS_3D])
+@pytest.mark.parametrize("stencil", [AXIS, RADIAL])
+def test_operator_matches_kronecker_form(dim, faces, stencil):
+    n = 4 if dim == 2 else 3
+    rng = np.random.default_rng(10)
+    P = OracleProblem(dim, n, stencil, faces, a=-0.3)
+    u = rng.uniform(-1, 1, P.shape)
+    got = P.apply(u)
+    ref = exact.kron_apply(dim, n, stencil, faces, -0.3, u)
+    assert rel_inf(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("stencil", [AXIS, RADIAL])
+@pytest.mark.parametrize("nu", [0, 1, 2])
+def test_operator_exact_on_quadratics_with_linear_coefficient(dim, stencil, nu):
+    # div(sigma grad u) for sigma linear and u quadratic is reproduced exactly
+    # by the average-of-faces form; a wrong average, weight or prefactor fails.
+    n = 5 if dim == 2 else 4
+    P0 = OracleProblem(dim, n, stencil)
+    grids = W.coords(n, dim)[::-1]  # x, y, (z)
+    rng = np.random.default_rng(3)
+    alpha, beta = 2.0, rng.uniform(-0.5, 0.5, dim)
+    sigma = alpha + sum(b * g for b, g in zip(beta, grids))
+    Q = rng.uniform(-1, 1, (dim, dim))
+    Q = Q + Q.T
+    lin = rng.uniform(-1, 1, dim)
+    u = sum(0.5 * Q[i, j] * grids[i] * grids[j] for i in range(dim) for j in range(dim))
+    u = u + sum(l * g for l, g in zip(lin, grids))
+    grad = [sum(Q[i, j] * grids[j] for j in range(dim)) + lin[i] for i in range(dim)]
+    ref = sigma * np.trace(Q) + sum(beta[i] * grad[i] for i in range(dim)) - 0.7 * u
+    P = OracleProblem(dim, n, stencil, a=-0.7, sigma=sigma)
+    got = P.apply_level(nu, u, sig_nu=sigma)
+    lam = 2 ** nu
+    sl = tuple(slice(lam, -lam, lam) for _ in range(dim))
+    assert np.max(np.abs(got[sl] - ref[sl])) < 1e-9 * max(1.0, np.max(np.abs(ref)))
+    del P0
+
+
+@pytest.mark.parametrize("dim,stencil", [(2, AXIS), (2, RADIAL), (3, AXIS), (3, RADIAL)])
+def test_operator_on_sine_mode_is_closed_form_symbol(dim, stencil):
+    n = 4
+    h = 1.0 / 2 ** n
+    p = (1, 3, 2)[:dim]
+    P = OracleProblem(dim, n, stencil)
+    grids = W.coords(n, dim)[::-1]
+    mode = np.prod([np.sin(pi * np.pi * g) for pi, g in zip(p, grids)], axis=0)
+    mu = [2 * np.cos(pi * np.pi * h) - 2 for pi in p]
+    if stencil == AXIS:
+        sym = sum(mu) / h ** 2
+    elif dim == 2:
+        sym = (mu[0] + mu[1] + mu[0] * mu[1] / 4) / h ** 2
+    else:
+        sym = (sum(mu) + 7 / 26 * (mu[0] * mu[1] + mu[1] * mu[2] + mu[0] * mu[2])
+               + mu[0] * mu[1] * mu[2] / 13) / h ** 2
+    got = P.apply(mode)
+    interior = tuple(slice(1, -1) for _ in range(dim))
+    assert np.max(np.abs(got[interior] - sym * mode[interior])) < 1e-10 * abs(sym)
+
+
+def test_radial_stencil_forward_euler_limit_is_papers_bound():
+    # Sec. 2 states the stable step dtau < h^2/2 for the Laplacian.  The
+    # highest grid mode is an eigenvector; its eigenvalue under the oracle's
+    # radial operator tends to -4/h^2 in 2D and 3D, so 2/|lambda_max| is the
+    # paper's bound (the axis stencil's is -4d/h^2, half the step).
+    for dim in (2, 3):
+        n = 5
+        h = 1.0 / 2 ** n
+        N = 2 ** n + 1
+        grids = W.coords(n, dim)[::-1]
+        mode = np.prod([np.sin((N - 2) * np.pi * g) for g in grids], axis=0)
+        for stencil, limit in ((RADIAL, -4.0), (AXIS, -4.0 * dim)):
+            Lm = OracleProblem(dim, n, stencil).apply(mode)
+            rq = np.sum(Lm * mode) / np.sum(mode * mode) * h ** 2
+            assert abs(rq - limit) < 0.02 * abs(limit), (dim, stencil, rq)
+
+
+# --------------------------------------------------------------- restriction
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("nu", [1, 2, 3])
+def test_restriction_equals_widened_hat_average(dim, nu):
+    # Algorithm 1's nested sums equal one direct average with the widened
+    # hat weights (lam - |j|)/lam^2 per axis (Sec. 2: "done directly or ...
+    # nested sums").
+    n = 5 if dim == 2 else 4
+    lam = 2 ** nu
+    rng = np.random.default_rng(nu)
+    P = OracleProblem(dim, n)
+    g = rng.uniform(-1, 1, P.shape)
+    got = P.restriction(g, nu)
+    w1 = np.array([(lam - abs(j)) / lam ** 2 for j in range(-lam + 1, lam)])
+    kern = w1
+    for _ in range(dim - 1):
+        kern = np.multiply.outer(kern, w1)
+    N = P.N
+    for c in itertools.product(range(lam, N - lam, lam), repeat=dim):
+        sl = tuple(slice(ci - lam + 1, ci + lam) for ci in c)
+        assert abs(got[c] - np.sum(kern * g[sl])) < 1e-14
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_restriction_of_cosine_is_closed_form_including_images(dim):
+    # cos(w x) is even about both faces, so its image extension is itself;
+    # R_lam cos(w x) = cos(w x) (1 + cos(w lam h))/2 per axis at every node.
+    n = 4
+    h = 1.0 / 2 ** n
+    P = OracleProblem(dim, n, faces="N" * 6)
+    grids = W.coords(n, dim)[::-1]
+    ks = (3, 1, 5)[:dim]
+    g = np.prod([np.cos(k * np.pi * x) for k, x in zip(ks, grids)], axis=0)
+    for nu in range(1, n):
+        got = P.restriction(g, nu)
+        fac = np.prod([np.prod([(1 + np.cos(k * np.pi * 2 ** m * h)) / 2 for m in range(nu)])
+                       for k in ks])
+        assert np.max(np.abs(got - fac * g)) < 1e-13
+
+
+def test_restriction_preserves_constants_and_linears():
+    n, dim = 5, 2
+    P = OracleProblem(dim, n)
+    Y, X = W.coords(n, dim)
+    lin = 0.3 + 1.7 * X - 0.4 * Y
+    for nu in range(n):
+        got = P.restriction(lin, nu)
+        lam = 2 ** nu
+        sl = (slice(lam, -lam, lam),) * 2  # level-nu nodes at least lam from the faces
+        assert np.max(np.abs(got[sl] - lin[sl])) < 1e-13
+        assert np.max(np.abs(P.restriction(np.full(P.shape, 2.5), nu) - 2.5)) < 1e-14
+
+
+# ------------------------------------------------------------- interpolation
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_interpolation_reproduces_multilinear_functions(dim):
+    n = 4
+    P = OracleProblem(dim, n)
+    grids = W.coords(n, dim)[::-1]
+    rng = np.random.default_rng(0)
+    coef = rng.uniform(-1, 1, 2 ** dim)
+    f = np.zeros(P.shape)
+    for b in range(2 ** dim):
+        term = coef[b] * np.ones(P.shape)
+        for ax in range(dim):
+            if (b >> ax) & 1:
+                term = term * grids[ax]
+        f += term
+    for nu in range(n):
+        lam = 2 ** nu
+        lv = np.zeros(P.shape)
+        sl = tuple(slice(None, None, lam) for _ in range(dim))
+        lv[sl] = f[sl]
+        assert np.max(np.abs(P.interp(nu, lv) - f)) < 1e-14
+
+
+def test_interpolation_of_one_node_is_tensor_hat():
+    n, dim, nu = 4, 2, 2
+    lam = 2 ** nu
+    P = OracleProblem(dim, n)
+    d = np.zeros(P.shape)
+    d[8, 4] = 1.0
+    got = P.interp(nu, d)
+    j, i = np.indices(P.shape)
+    ref = np.clip(1 - np.abs(j - 8) / lam, 0, None) * np.clip(1 - np.abs(i - 4) / lam, 0, None)
+    assert np.max(np.abs(got - ref)) == 0.0
+
+
+# --------------------------------------------------------------- relaxation
+
+@pytest.mark.parametrize("dim,stencil", [(2, AXIS), (2, RADIAL), (3, RADIAL)])
+def test_one_relaxation_amplifies_a_mode_by_closed_form_factor(dim, stencil):
+    n = 4
+    h = 1.0 / 2 ** n
+    P = OracleProblem(dim, n, stencil)
+    grids = W.coords(n, dim)[::-1]
+    p = (2, 5, 3)[:dim]
+    mode = np.prod([np.sin(pi * np.pi * g) for pi, g in zip(p, grids)], axis=0)
+    u1, _ = P.relax_interp(0, mode, np.zeros(P.shape))
+    sym = exact.operator_symbol(dim, n, stencil, "D" * 6, 0.0)[tuple(pi - 1 for pi in p[::-1])]
+    # diagonal magnitude for sigma = 1: C / h^2 * sum of weights
+    Dg = {(2, AXIS): 4.0, (2, RADIAL): 0.5 * (4 + 4 / 2),
+          (3, RADIAL): (3.0 / 13.0) * (6 + 12 / 2 + 8 / 3)}[(dim, stencil)] / h ** 2
+    amp = 1 + P.theta * sym / Dg
+    assert np.max(np.abs(u1 - amp * mode)) < 1e-13
+
+
+def test_dirichlet_nodes_take_the_prescribed_variation():
+    n, dim = 4, 2
+    P = OracleProblem(dim, n)
+    rng = np.random.default_rng(1)
+    G = rng.uniform(-1, 1, P.shape)
+    u = rng.uniform(-1, 1, P.shape)
+    m = P.dirichlet_mask()
+    out, _ = P.relax_interp(0, u, np.zeros(P.shape), G=G)
+    assert np.array_equal(out[m], G[m])
+
+
+# -------------------------------------------------------- cycle / recurrence
+
+def test_cycle_is_linear_in_the_source():
+    P = OracleProblem(2, 5, RADIAL, "DDNN", a=-0.2,
+                      sigma=np.exp(np.random.default_rng(2).uniform(-1, 1, (33, 33))))
+    rng = np.random.default_rng(4)
+    s1, s2 = rng.uniform(-1, 1, P.shape), rng.uniform(-1, 1, P.shape)
+    e1, e2 = P.cycle(s1), P.cycle(s2)
+    e12 = P.cycle(1.5 * s1 - 0.25 * s2)
+    assert rel_inf(e12, 1.5 * e1 - 0.25 * e2) < 1e-13
+
+
+def test_poisson2d_sine_converges_to_closed_form_and_dst_solution():
+    wl = W.poisson2d_sine(n=7)
+    P = OracleProblem(2, wl.n, wl.stencil, wl.faces, wl.a)
+    u, info = P.solve(wl.f, tol=1e-14)
+    assert info["status"] == 0 and info["relres"] <= 1e-14
+    ref = exact.spectral_solve(2, wl.n, AXIS, wl.faces, 0.0, wl.f)
+    assert rel_inf(u, ref) < 1e-12
+    # without the noise, the discrete solution is a multiple of sin sin
+    h = 1.0 / 2 ** wl.n
+    Y, X = W.coords(wl.n, 2)
+    ss = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    lam_h = 8.0 / h ** 2 * np.sin(np.pi * h / 2) ** 2
+    u0, info0 = P.solve(-2 * np.pi ** 2 * ss, tol=1e-15)
+    assert rel_inf(u0, (2 * np.pi ** 2 / lam_h) * ss) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", [
+    (2, 7, AXIS, "DDNN"), (2, 6, RADIAL, "DDDD"), (2, 6, RADIAL, "NNDD"),
+    (3, 4, RADIAL, "DDDDDD"), (3, 4, AXIS, "DDNNDD"), (3, 4, RADIAL, "NNNNDD")])
+def test_converged_solution_matches_spectral_solve(dim, n, stencil, faces):
+    rng = np.random.default_rng(dim * 10 + n)
+    P = OracleProblem(dim, n, stencil, faces, a=-0.5)
+    f = rng.uniform(-1, 1, P.shape)
+    G = rng.uniform(-1, 1, P.shape)
+    u, info = P.solve(f, G=G, tol=1e-15)
+    assert info["status"] == 0
+    ref = exact.spectral_solve(dim, n, stencil, faces, -0.5, f, G)
+    assert rel_inf(u, ref) < 1e-12
+    assert info["relres_true"] < 1e-11
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", [
+    (2, 4, AXIS, "DDDD"), (2, 4, RADIAL, "DNND"), (2, 4, AXIS, "DDNN"),
+    (3, 3, RADIAL, "DDDDDD"), (3, 3, RADIAL, "DDNNDN"), (3, 3, AXIS, "NDDDDD")])
+def test_heterogeneous_converged_solution_matches_dense_lu(dim, n, stencil, faces):
+    # 17^2 / 9^3 grids: dense LU of the assembled operator
+    wl = W.random_problem(dim, n, stencil, faces, seed=7 + n, hetero=True, a=-0.25)
+    P = OracleProblem(dim, n, stencil, faces, a=wl.a, sigma=wl.sigma)
+    u, info = P.solve(wl.f, G=wl.G, tol=1e-15, max_cycles=400)
+    assert info["status"] == 0
+    ref = exact.direct_solve(dim, n, stencil, faces, wl.a, wl.f, wl.sigma, wl.G)
+    assert rel_inf(u, ref) < 1e-12
+
+
+def test_sphere_medium_converges_to_cg_solution():
+    n = 4  # 17^3, contrast up to 80
+    eps = W.sphere_medium(n, seed=3)
+    G = W.capacitor_bc(n)
+    f = np.zeros_like(eps)
+    P = OracleProblem(3, n, RADIAL, "DDDDDD", a=-0.5, sigma=eps)
+    u, info = P.solve(f, G=G, tol=1e-15, max_cycles=600)
+    assert info["status"] == 0
+    ref = exact.cg_solve(3, n, RADIAL, -0.5, f, eps, G, rtol=1e-15)
+    assert rel_inf(u, ref) < 1e-11
+
+
+def test_one_dimensional_data_invariant():
+    # f = f(x), Dirichlet x-walls, Neumann elsewhere: the discrete solution is
+    # the 1D tridiagonal solution, and -- because the widened hat average of
+    # second differences is the stride-lam second difference -- the
+    # pseudo-residual of that solution vanishes on every level.
+    for dim, stencil, faces in [(2, AXIS, "DDNN"), (2, RADIAL, "DDNN"), (3, RADIAL, "DDNNNN")]:
+        n = 5 if dim == 2 else 4
+        N = 2 ** n + 1
+        h = 1.0 / 2 ** n
+        rng = np.random.default_rng(5)
+        fx = rng.uniform(-1, 1, N)
+        # 1D Thomas solve of (u[i-1] - 2u[i] + u[i+1])/h^2 = fx[i], u[0] = u[N-1] = 0
+        ab = np.zeros((3, N - 2))
+        ab[0, 1:] = 1.0 / h ** 2
+        ab[1, :] = -2.0 / h ** 2
+        ab[2, :-1] = 1.0 / h ** 2
+        ux = np.zeros(N)
+        ux[1:-1] = sla.solve_banded((1, 1), ab, fx[1:-1])
+        shape = (N,) * dim
+        f = np.broadcast_to(fx, shape).copy()
+        ustar = np.broadcast_to(ux, shape).copy()
+        P = OracleProblem(dim, n, stencil, faces)
+        u, info = P.solve(f, tol=1e-15)
+        assert rel_inf(u, ustar) < 1e-12
+        for nu in range(n):
+            g = P.restriction(f, nu)
+            _, pres = P.relax_interp(nu, ustar, g)
+            assert pres < 1e-10 * np.max(np.abs(f)), (dim, stencil, nu, pres)
+
+
+def test_paper_section31_manufactured_solution_second_order():
+    # eq. (6)-(9): L1 error of the converged discrete solution against the
+    # polynomial solution decreases at second order.
+    errs = []
+    for n in (4, 5, 6, 7):
+        Y, X = W.coords(n, 2)
+        uex = -X ** 2 * Y ** 2 * (1 - X ** 2) * (1 - Y ** 2)
+        f = -2 * (Y ** 2 * (1 - 6 * X ** 2) * (1 - Y ** 2) + X ** 2 * (1 - 6 * Y ** 2) * (1 - X ** 2))
+        P = OracleProblem(2, n, AXIS)
+        u, info = P.solve(f, tol=1e-13)
+        assert info["status"] == 0
+        errs.append(np.sum(np.abs(u - uex)) / np.sum(np.abs(uex)))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(abs(o - 2.0) < 0.1 for o in orders), orders
+
+
+def test_operation_count_grows_linearly():
+    # Sec. 1/abstract: the total number of operations scales linearly with the
+    # number of nodes.  Level-node relaxations to 1e-12 per node stay flat.
+    per_node = []
+    for n in (5, 6, 7, 8):
+        wl = W.random_problem(2, n, AXIS, "DDDD", seed=3, hetero=False, dirichlet_values=False)
+        P = OracleProblem(2, n, AXIS)
+        u, info = P.solve(wl.f, tol=1e-12)
+        assert info["status"] == 0
+        per_node.append(info["relax_updates"] / (2 ** n + 1) ** 2)
+    assert max(per_node) / min(per_node) < 1.2, per_node
+
+
+def test_failure_statuses():
+    wl = W.random_problem(2, 4, AXIS, "DDDD", seed=1, hetero=False)
+    # unstable pseudo-time step (well above the forward-Euler limit) diverges
+    P = OracleProblem(2, 4, AXIS, theta=2.5)
+    _, info = P.solve(wl.f, tol=1e-12, max_cycles=50)
+    assert info["status"] == -5
+    # not enough cycles
+    P = OracleProblem(2, 4, AXIS)
+    _, info = P.solve(wl.f, tol=1e-12, max_cycles=1)
+    assert info["status"] == -7 and info["cycles"] == 1
+    # zero data: nothing to solve
+    u, info = P.solve(np.zeros(P.shape), tol=1e-12)
+    assert info["status"] == 0 and info["cycles"] == 0 and not np.any(u)
+
+
+# ------------------------------------------------------------------ adjoint
+
+def _loss(u, ut, mask):
+    d = np.where(mask, 0.0, u - ut)
+    return 0.5 * np.sum(d * d)
+
+
+def test_operator_is_symmetric_for_dirichlet_faces():
+    wl = W.random_problem(3, 3, RADIAL, "DDDDDD", seed=2, hetero=True)
+    P = OracleProblem(3, 3, RADIAL, a=-0.5, sigma=wl.sigma)
+    m = P.dirichlet_mask()
+    rng = np.random.default_rng(9)
+    x = np.where(m, 0, rng.uniform(-1, 1, P.shape))
+    y = np.where(m, 0, rng.uniform(-1, 1, P.shape))
+    lhs, rhs = np.sum(P.apply(x) * y), np.sum(x * P.apply(y))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_adjoint_gradients_match_finite_differences():
+    n = 3
+    wl = W.random_problem(3, n, RADIAL, "DDDDDD", seed=11, hetero=True, a=-0.5)
+    P = OracleProblem(3, n, RADIAL, a=-0.5, sigma=wl.sigma)
+    m = P.dirichlet_mask()
+    ut = np.random.default_rng(12).uniform(-1, 1, P.shape)
+    u, _ = P.solve(wl.f, G=wl.G, tol=1e-14, max_cycles=200)
+    g = np.where(m, 0.0, u - ut)
+    lam, _ = P.solve(g, tol=1e-14, max_cycles=200)
+    lam[m] = 0.0
+    gsig = P.coeff_grad(u, lam)
+    rng = np.random.default_rng(13)
+    for _ in range(5):
+        node = tuple(rng.integers(1, 2 ** n, 3))
+        # dL/df: the loss is quadratic in f, so the central difference is exact
+        fp, fm = wl.f.copy(), wl.f.copy()
+        fp[node] += 1.0
+        fm[node] -= 1.0
+        up, _ = P.solve(fp, G=wl.G, tol=1e-14, max_cycles=200)
+        um, _ = P.solve(fm, G=wl.G, tol=1e-14, max_cycles=200)
+        fd = (_loss(up, ut, m) - _loss(um, ut, m)) / 2.0
+        assert abs(fd - lam[node]) < 1e-8 * max(1.0, abs(fd))
+        # dL/dsigma: central difference with a small relative step
+        d = 1e-4 * wl.sigma[node]
+        sp_, sm_ = wl.sigma.copy(), wl.sigma.copy()
+        sp_[node] += d
+        sm_[node] -= d
+        up, _ = OracleProblem(3, n, RADIAL, a=-0.5, sigma=sp_).solve(wl.f, G=wl.G, tol=1e-14,
+                                                                      max_cycles=200)
+        um, _ = OracleProblem(3, n, RADIAL, a=-0.5, sigma=sm_).solve(wl.f, G=wl.G, tol=1e-14,
+                                                                      max_cycles=200)
+        dd = np.where(m, 0.0, up - um)
+        s = np.where(m, 0.0, up + um - 2 * ut)
+        fd = 0.5 * np.sum(dd * s) / (2 * d)
+        assert abs(fd - gsig[node]) < 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(gsig)))
+
+
+def test_cycle_is_the_golden_schedule_of_pinned_primitives():
+    # Algorithm 3 composed by hand from the separately pinned pieces: the
+    # visit list of tests/golden (n = 5), restriction(nu) of the source and of
+    # the coefficient (Algorithm 1), and relaxation-interpolation (Algorithm 2).
+    gold = _read_schedule_golden()["n_r=2"]
+    wl = W.random_problem(2, 5, RADIAL, "DDNN", seed=21, hetero=True, a=-0.3)
+    P = OracleProblem(2, 5, RADIAL, "DDNN", a=wl.a, sigma=wl.sigma)
+    e, pres, trace = P.cycle(wl.f, G=wl.G, with_pres=True, with_trace=True)
+    assert len(trace) == len(gold)
+    state = np.zeros(P.shape)
+    for v, (nu, c) in enumerate(gold):
+        g = P.restriction(wl.f, nu)
+        sig = P.restriction(wl.sigma, nu)
+        for _ in range(c):
+            state, pr = P.relax_interp(nu, state, g, sig, wl.G)
+        assert np.array_equal(state, trace[v]), v
+        assert pr == pres[v]
+    assert np.array_equal(state, e)

@@ -1,0 +1,135 @@
+"""Benchmark: time-to-tolerance of the SGML solve on one MI355X.
+
+One step = one full solve (every cycle of Algorithm 3 plus the FP64
+residual recurrence) to relative residual 1e-12 on the 4097^2 2D Poisson
+workload with mixed Dirichlet (x-walls) / Neumann (y-walls) faces and 64
+Gaussian blobs, inputs resident in HBM.  The headline value is the mixed
+precision solve (FP32 cycle, FP64 refinement); the plain FP64 solve of the
+same workload is timed beside it.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GNodes/s to rel. residual 1e-12 (FP64 vs FP32+FP64-refine); % HBM peak"
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="poisson2d_blobs")
+    return ap.parse_args()
+
+
+def timed_solves(plan, f, G, u, precision, steps, profile):
+    import torch
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = plan.solve(f, G, u, tol=TOL, max_cycles=200, precision=precision, profile=profile)
+        stats.append(st)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, stats
+
+
+def cpu_baseline(wl, cycles):
+    """The FP64 oracle on the host cores: one cycle of the same workload,
+    scaled by the cycle count the solve needs."""
+    from oracle.core import OracleProblem, threads
+    P = OracleProblem(wl.dim, wl.n, wl.stencil, wl.faces, wl.a, wl.sigma)
+    t0 = time.perf_counter()
+    P.cycle(wl.f, G=wl.G)
+    t_cycle = time.perf_counter() - t0
+    t_solve = t_cycle * cycles
+    return {"value": wl.nodes / t_solve / 1e9, "unit": "GNodes/s", "cores": threads(),
+            "kind": "oracle",
+            "sample": f"one cycle of the FP64 oracle on the same {wl.N}^{wl.dim} input "
+                      f"({t_cycle:.2f} s), times the {cycles} cycles the FP64 solve needs"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1703_07206_amd import sgml
+    from paper_1703_07206_amd import workloads as W
+
+    wl = W.CONFIGS[args.workload]()
+    dev = lambda x: None if x is None else torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa
+    f, G, sigma = dev(wl.f), dev(wl.G), dev(wl.sigma)
+    plan = sgml.Plan(wl.dim, wl.n, wl.stencil, wl.faces, wl.a, sigma, precision=sgml.MIXED)
+    u = torch.empty_like(f)
+    u64 = torch.empty_like(f)
+
+    for _ in range(args.warmup):
+        plan.solve(f, G, u, tol=TOL, max_cycles=200, precision=sgml.MIXED)
+        plan.solve(f, G, u64, tol=TOL, max_cycles=200, precision=sgml.FP64)
+    t_mix, st_mix = timed_solves(plan, f, G, u, sgml.MIXED, args.steps, True)
+    t_64, st_64 = timed_solves(plan, f, G, u64, sgml.FP64, args.steps, True)
+    print(f"# mixed: {t_mix * 1e3:.3f} ms/solve, {st_mix[-1]['cycles']} cycles; "
+          f"fp64: {t_64 * 1e3:.3f} ms/solve, {st_64[-1]['cycles']} cycles", file=sys.stderr, flush=True)
+
+    # accuracy of both results
+    _, r_mix, norm0 = plan.residual(f, u, G=G)
+    _, r_64, _ = plan.residual(f, u64, G=G)
+    diff = float((u - u64).abs().max() / u64.abs().max())
+
+    # dominant kernel: the level-0 relaxation, 12 B/node (FP32 read e, read g, write e)
+    sm = st_mix[-1]
+    sweep_ms = sm["sweep0_ms"] / max(1, sm["sweep0_launches"])
+    bytes_per_launch = 12.0 * wl.nodes
+    achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
+    s6 = st_64[-1]
+    sweep64_ms = s6["sweep0_ms"] / max(1, s6["sweep0_launches"])
+
+    out = {
+        "metric": METRIC,
+        "value": wl.nodes / t_mix / 1e9,
+        "unit": "GNodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mix * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name} {wl.N}^{wl.dim}", "nodes": wl.nodes,
+                   "stencil": "radial" if wl.stencil else "axis", "faces": wl.faces,
+                   "tol": TOL, "precision": "fp32 cycle + fp64 refinement", "n_r": 2},
+        "fp64": {"value": wl.nodes / t_64 / 1e9, "ms_per_step": t_64 * 1e3,
+                 "cycles": s6["cycles"], "relres_true": r_64 / norm0,
+                 "sweep0_us": sweep64_ms * 1e3,
+                 "sweep0_GBs": 24.0 * wl.nodes / (sweep64_ms * 1e-3) / 1e9},
+        "mixed": {"cycles": sm["cycles"], "relres": sm["relres"], "relres_true": r_mix / norm0,
+                  "rel_diff_vs_fp64": diff, "sweep0_us": sweep_ms * 1e3,
+                  "boundary_us": 1e3 * sm["boundary_ms"] / max(1, sm["boundary_launches"])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "level-0 relaxation (FP32, 5-point)",
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, s6["cycles"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

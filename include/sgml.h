@@ -1,0 +1,191 @@
+/*
+ * sgml.h -- C-ABI of the MI355X single-grid multi-level (SGML) solver.
+ *
+ * Method: Becerra-Sagredo, Mandujano and Malaga, "A GPU-based Multi-level
+ * Algorithm for Boundary Value Problems" (2016).  The library solves
+ *
+ *     dL(u) = f,    L = div(sigma grad) + a        (Sec. 2 eq. (1), Sec. 3)
+ *
+ * on the unit square / cube with N = 2^n + 1 nodes per axis (Sec. 2), by
+ * the saw-like refining cycle of Algorithm 3 built from the restriction of
+ * Algorithm 1 (eq. (3) / (4)) and the relaxation-interpolation of
+ * Algorithm 2, repeated on accumulated residuals (Sec. 2, last paragraphs)
+ * until the relative residual of Sec. 3.1 reaches the tolerance.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are dense, row-major, N^d doubles, index (k*N + j)*N + i with i
+ *     along x (fastest), j along y, k along z (absent in 2D); node (i,j,k)
+ *     sits at (i h, j h, k h), h = 2^-n.  Boundary nodes are included.
+ *   - Faces are ordered x-, x+, y-, y+, z-, z+.  A node on any Dirichlet face
+ *     is a Dirichlet node (it carries no equation); every other node is an
+ *     unknown.  Neumann faces are homogeneous (zero normal derivative) and
+ *     are imposed by node images (Sec. 2: reflection about the face).
+ *   - "device" pointers are HIP device memory of the device that is current
+ *     when the plan is created; "host" pointers are ordinary host memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is stream-ordered; entry points that return host results
+ *     synchronise that stream before returning.
+ *   - The caller owns every buffer.  The library allocates no device
+ *     memory; a plan borrows a caller-provided device workspace for its
+ *     lifetime and a small block of pinned host memory of its own.
+ *   - Errors are returned as sgml_status values; nothing is thrown.  A plan
+ *     is not thread-safe: one host thread at a time per plan.
+ */
+#ifndef SGML_H
+#define SGML_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGML_OK = 0,
+    SGML_E_ARG = -1,         /* invalid argument (NULL, bad enum, bad size) */
+    SGML_E_SHAPE = -2,       /* grid not of the form N = 2^n + 1 supported here */
+    SGML_E_WORKSPACE = -3,   /* workspace missing, too small or misaligned */
+    SGML_E_HIP = -4,         /* a HIP runtime call failed */
+    SGML_E_DIVERGED = -5,    /* residual non-finite or grew above 1e3 x initial */
+    SGML_E_STAGNATED = -6,   /* residual fell by less than 2x over 3 cycles */
+    SGML_E_MAXCYCLES = -7,   /* max_cycles reached above the tolerance */
+    SGML_E_UNSUPPORTED = -8  /* valid request outside what this build implements */
+} sgml_status;
+
+enum { SGML_DIRICHLET = 0, SGML_NEUMANN = 1 };
+
+/* Finite-difference molecule of dL.
+ *   SGML_AXIS:   5-point (2D) / 7-point (3D) -- the "simple molecules"
+ *                discussed in the conclusions.
+ *   SGML_RADIAL: 9-point (2D) / 27-point (3D) radial stencil of eq. (5)
+ *                (Fig. 2): every neighbour d contributes
+ *                (2d/(3^d-1)) / h^2 * (sigma_d + sigma_c)/2 * (u_d - u_c) / |d|^2. */
+enum { SGML_AXIS = 0, SGML_RADIAL = 1 };
+
+/* Arithmetic of the cycle (restriction and relaxation-interpolation).
+ *   SGML_FP64:  everything in FP64.
+ *   SGML_MIXED: the cycle runs in FP32 on the residual scaled by a power of
+ *               two; the residual recurrence, its norm and the collected
+ *               solution stay FP64 (outer iterative refinement). */
+enum { SGML_FP64 = 0, SGML_MIXED = 1 };
+
+/* Visit order of Algorithm 3.  SGML_SCHEDULE_ONCE: lines 9-10 (the level-0
+ * relaxations) run once after the loop over teeth; SGML_SCHEDULE_EACH: they
+ * run after every tooth. */
+enum { SGML_SCHEDULE_ONCE = 0, SGML_SCHEDULE_EACH = 1 };
+
+typedef struct {
+    int dim;          /* 2 or 3 */
+    int n;            /* N = 2^n + 1; 2 <= n <= 13 (2D), 2 <= n <= 10 (3D) */
+    int stencil;      /* SGML_AXIS or SGML_RADIAL */
+    int face[6];      /* SGML_DIRICHLET or SGML_NEUMANN per face (2D: first 4) */
+    double a;         /* constant term of L; a <= 0 keeps forward Euler stable */
+    double theta;     /* pseudo-time step dtau = theta / D(x), D the local
+                         diagonal (Sec. 2, Sec. 3.4); <= 0 selects the default
+                         0.8 (5-pt), 6/7 (7-pt), 1.0 (radial) */
+} sgml_problem;
+
+typedef struct {
+    double tol;       /* stop when max|r| / max|r_0| <= tol (Sec. 3.1) */
+    int max_cycles;   /* >= 1 */
+    int n_r;          /* max relaxation-interpolations per visit (Sec. 3.1
+                         runs use 2); <= 0 means full doubling (Fig. 1) */
+    int schedule;     /* SGML_SCHEDULE_ONCE or SGML_SCHEDULE_EACH */
+    int precision;    /* SGML_FP64 or SGML_MIXED; must not exceed the plan's */
+    int record_pres;  /* 1: keep the per-visit pseudo-residuals of the last cycle */
+    int profile;      /* 1: time every level-0 sweep and boundary pass with stream
+                         events (sweep0_ms, boundary_ms in the stats) */
+} sgml_opts;
+
+#define SGML_HIST 512
+#define SGML_MAX_VISITS 128
+typedef struct {
+    int status;                     /* same value as returned */
+    int cycles;                     /* cycles run */
+    double norm0;                   /* max|f - dL(u_init)| over unknowns, u_init = G on
+                                       Dirichlet nodes and 0 elsewhere */
+    double relres;                  /* recursive residual max|r_i| / norm0 */
+    double history[SGML_HIST];      /* relres after each cycle */
+    int visits;                     /* visits per cycle */
+    double pres[SGML_MAX_VISITS];   /* per-visit pseudo-residual of the last
+                                       relaxation, last cycle (record_pres) */
+    long long node_updates;         /* level-node relaxations performed */
+    float ms;                       /* device time of the solve, stream events */
+    int sweep0_launches;            /* level-0 relaxation launches (profile) */
+    float sweep0_ms;                /* their summed device time (profile) */
+    int boundary_launches;          /* cycle-end passes (profile) */
+    float boundary_ms;              /* their summed device time (profile) */
+} sgml_stats;
+
+typedef struct sgml_plan sgml_plan;
+
+/* Bytes of device workspace a plan for `prob` at `precision` needs (the
+ * MIXED size also serves FP64 solves).  Returns 0 for an invalid problem.
+ * Workspace must be 256-byte aligned. */
+size_t sgml_workspace_bytes(const sgml_problem *prob, int precision);
+
+/* Create a plan: validates prob (SGML_E_ARG / SGML_E_SHAPE), checks that
+ * `workspace` (device, ws_bytes long, 256-byte aligned) holds at least
+ * sgml_workspace_bytes(prob, precision) (SGML_E_WORKSPACE), and records the
+ * current device.  The plan uses sigma = 1 until sgml_plan_set_coeffs. */
+sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *workspace,
+                             size_t ws_bytes, sgml_plan **out);
+
+/* Bind the coefficient field sigma (device, N^d doubles, sigma > 0) or NULL
+ * for sigma = 1, and build its per-level restrictions (Algorithm 1 applied
+ * to the coefficient, "restricted sources and coefficients", Sec. 2) in the
+ * workspace.  The plan borrows sigma: it must stay valid and unchanged
+ * while the plan solves, computes residuals or gradients. */
+sgml_status sgml_plan_set_coeffs(sgml_plan *plan, const double *sigma, void *stream);
+
+/* Solve dL(u) = f (Sec. 2) to opts->tol.
+ *   f: device, N^d; values at Dirichlet nodes are ignored.
+ *   G: device, N^d Dirichlet values (read at Dirichlet nodes only), or NULL
+ *      for zero.  Imposed through the variation in the first cycle (Sec. 2).
+ *   u: device, N^d, output (overwritten; may not alias f or G).
+ *   stats: host, optional.
+ * Returns SGML_OK on convergence, else a failure status with u holding the
+ * last collected solution.  Synchronises the stream once per cycle (stop
+ * test). */
+sgml_status sgml_solve(sgml_plan *plan, const double *f, const double *G, double *u,
+                       const sgml_opts *opts, void *stream, sgml_stats *stats);
+
+/* Residual of a candidate solution (Sec. 2 recurrence, Sec. 3.1 norm):
+ *   r = f - dL(u) at unknowns, 0 at Dirichlet nodes (r: device N^d or NULL);
+ *   *rmax = max |r| (host, optional);
+ *   *norm0 = max |f - dL(u_init)| (host, optional; u_init = G on Dirichlet
+ *   nodes, 0 elsewhere).  u must hold the Dirichlet values on Dirichlet
+ *   nodes for r to be the residual of the boundary value problem. */
+sgml_status sgml_residual(sgml_plan *plan, const double *f, const double *G, const double *u,
+                          double *r, double *rmax, double *norm0, void *stream);
+
+/* Adjoint solve dL^T(lambda) = g on the unknowns with lambda = 0 on
+ * Dirichlet nodes.  For all-Dirichlet faces the operator is symmetric and
+ * this is sgml_solve with source g and zero Dirichlet values.  Other faces:
+ * SGML_E_UNSUPPORTED.  g, lambda: device N^d. */
+sgml_status sgml_adjoint(sgml_plan *plan, const double *g, double *lambda, const sgml_opts *opts,
+                         void *stream, sgml_stats *stats);
+
+/* Gradient of a loss with respect to sigma (all-Dirichlet faces only),
+ * given the solution u and the adjoint lambda of dLoss/du:
+ *   grad[m] = -C/(2h^2) sum_k w_k (u[m+d_k] - u[m]) (lambda[m] - lambda[m+d_k])
+ * over neighbours inside the grid (implicit-function theorem on dL(u) = f).
+ * u, lambda, grad: device N^d. */
+sgml_status sgml_coeff_grad(sgml_plan *plan, const double *u, const double *lambda, double *grad,
+                            void *stream);
+
+/* Visit list of Algorithm 3 for N = 2^n + 1: level[v], count[v] for
+ * v < min(*len, cap); *len receives the full length.  Host only. */
+sgml_status sgml_schedule(int n, int n_r, int schedule, int *level, int *count, int cap, int *len);
+
+/* Static description of a status code. */
+const char *sgml_status_string(sgml_status status);
+
+/* Release the plan's host resources (the workspace and sigma stay the
+ * caller's). */
+void sgml_plan_destroy(sgml_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGML_H */

@@ -180,6 +180,11 @@ class OracleProblem:
         return out
 
 
+def threads():
+    """Number of host threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
+
+
 def schedule(n, n_r=2, reading=0):
     cap = 8 * n + 16
     lev = np.zeros(cap, dtype=np.int32)

@@ -738,3 +738,11 @@ int orc_dirichlet_mask(const orc_problem *p, uint8_t *mask)
 }
 
 int orc_hist_cap(void) { return ORC_HIST; }
+
+/* Threads the parallel loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

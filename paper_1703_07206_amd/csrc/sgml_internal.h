@@ -1,0 +1,84 @@
+// sgml_internal.h -- shared declarations of the SGML HIP library (not part
+// of the public C-ABI, which is include/sgml.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sgml {
+
+// Geometry and operator constants of one level of the nested grid
+// (Sec. 2: level nu holds the nodes whose indices are multiples of
+// lam = 2^nu; stored compactly as m^d values, m = 2^(n-nu) + 1).
+struct Level {
+    int m;            // nodes per axis on this level
+    int lam;          // stride of the level on the full grid
+    int N;            // nodes per axis of the full grid
+    unsigned dir;     // bit f set when face f (x-, x+, y-, y+, z-, z+) is Dirichlet
+    double scale;     // C / (lam h)^2 of the stencil
+    double a;         // constant term of L
+    double theta;     // dtau = theta / D
+};
+
+// A max-reduction target: kRedSlots partial maxima, kRedStride u64 apart
+// (one 128-byte line each), so that the per-block atomics of a large grid
+// spread over many L2 lines instead of serialising on one address.  The
+// host takes the max of the slots.
+constexpr int kRedSlots = 64;
+constexpr int kRedStride = 16;
+constexpr int kRedWords = kRedSlots * kRedStride;
+
+// Which kernel variant: dimension, stencil, heterogeneous coefficient.
+struct Variant {
+    int dim;          // 2 or 3
+    int radial;       // 0 axis stencil, 1 radial stencil
+    int sigma;        // 0: sigma = 1, 1: coefficient array
+};
+
+// Precision-generic launchers (T = double or float); all enqueue on `st`.
+template <typename T>
+void launch_fill(T *p, size_t count, T value, hipStream_t st);
+
+template <typename T>
+void launch_sweep(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
+                  const double *G, unsigned long long *pres, hipStream_t st);
+
+template <typename T>
+void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first,
+                    hipStream_t st);
+
+template <typename T>
+void launch_inject(int dim, int mc, const T *ef, T *ec, hipStream_t st);
+
+template <typename Tin, typename Tout>
+void launch_restrict(int dim, int mc, const Tin *fine, Tout *coarse, hipStream_t st);
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *in, Tout *out, size_t count, hipStream_t st);
+
+// FP64 work on the full grid (level 0).
+template <typename T>
+void launch_boundary(const Variant &v, const Level &L, const T *e, double escale, const double *G,
+                     const double *sigma, double *u, double *s, T *shat, double shat_scale,
+                     unsigned long long *norm, hipStream_t st);
+
+void launch_init(const Variant &v, const Level &L, const double *f, const double *G,
+                 const double *sigma, double *s, double *u, unsigned long long *norm0,
+                 hipStream_t st);
+
+template <typename T>
+void launch_source_cast(const Level &L, int dim, const double *s, T *shat, double scale,
+                        hipStream_t st);
+
+void launch_set_dirichlet(const Level &L, int dim, const double *G, double *u, hipStream_t st);
+
+void launch_residual(const Variant &v, const Level &L, const double *f, const double *G,
+                     const double *sigma, const double *u, double *r, unsigned long long *rmax,
+                     unsigned long long *norm0, hipStream_t st);
+
+void launch_coeff_grad(const Variant &v, const Level &L, const double *u, const double *lam,
+                       double *grad, hipStream_t st);
+
+}  // namespace sgml

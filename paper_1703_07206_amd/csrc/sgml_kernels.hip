@@ -1,0 +1,665 @@
+// sgml_kernels.hip -- HIP kernels of the SGML solver for gfx950.
+//
+// Every routine of the method is bandwidth bound (a few flops per byte), so
+// the kernels are plain coalesced streaming kernels: one lane per node along
+// x (the contiguous axis), 64-lane wavefronts covering 64 consecutive nodes
+// of a row.  Stencil neighbours are re-read through L1/L2, which holds the
+// rows above and below.
+//
+// Levels (Sec. 2): level nu holds the nodes whose indices are multiples of
+// lam = 2^nu.  The full grid keeps level 0; every coarser level is stored
+// compactly (m^d values, m = 2^(n-nu) + 1), so that a relaxation at level nu
+// reads and writes only its own nodes.  Algorithm 2 interpolates each
+// variation of level nu to all other nodes; here that interpolation is
+// deferred: a level keeps its values, and when the schedule moves to the next
+// finer level the pending variation (coarse value minus the finer level's
+// stale copy at the coarse nodes) is interpolated once (k_prolong).  Since a
+// relaxation at level nu reads only level-nu nodes and the hat interpolation
+// is linear and nested (interpolating level nu to level nu-1 and then on
+// reproduces the direct interpolation), this gives the values the full-grid
+// formulation gives, up to rounding order.
+#include "sgml_internal.h"
+
+#include <algorithm>
+#include <type_traits>
+#include <utility>
+
+namespace sgml {
+
+namespace {
+
+constexpr int BX = 64;  // one wavefront along x
+constexpr int BY = 4;
+
+__device__ __forceinline__ size_t lin(int i, int j, int k, int m)
+{
+    return ((size_t)k * (size_t)m + (size_t)j) * (size_t)m + (size_t)i;
+}
+
+// Image of a coordinate across a face (node reflection).  For unknown nodes
+// it only triggers at Neumann faces: an unknown is never on a Dirichlet face.
+__device__ __forceinline__ int mir(int c, int m)
+{
+    c = c < 0 ? -c : c;
+    return c > m - 1 ? 2 * (m - 1) - c : c;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool is_dir(int i, int j, int k, int m, unsigned dir)
+{
+    bool d = ((dir & 1u) && i == 0) || ((dir & 2u) && i == m - 1) || ((dir & 4u) && j == 0) ||
+             ((dir & 8u) && j == m - 1);
+    if (DIM == 3) d = d || ((dir & 16u) && k == 0) || ((dir & 32u) && k == m - 1);
+    return d;
+}
+
+// Order-independent max of non-negative doubles (and NaN, whose bit pattern
+// with a clear sign bit exceeds that of +inf): integer max of the bits,
+// accumulated per block and then into one slot of a reduction target.
+__device__ __forceinline__ unsigned long long dbits(double x)
+{
+    return (unsigned long long)__double_as_longlong(fabs(x));
+}
+
+__device__ __forceinline__ void block_max(unsigned long long v, unsigned long long *out)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    __shared__ unsigned long long wmax[16];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    if ((tid & 63) == 0) wmax[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < (nthr + 63) / 64; ++w) v = wmax[w] > v ? wmax[w] : v;
+        const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        if (v) atomicMax(out + (b % kRedSlots) * kRedStride, v);
+    }
+    __syncthreads();  // wmax may be reused by a second reduction in the same kernel
+}
+
+// Stride-lam finite-difference operator of L = div(sigma grad) + a at a node
+// of a compact level array (eq. (5) and the axis molecule):
+//   Lu = scale * sum_k w_k (sigma_k + sigma_c)/2 (u_k - u_c) + a u_c,
+//   D  = scale * sum_k w_k (sigma_k + sigma_c)/2 - a,
+// w = 1 for face neighbours, 1/2 for edge and 1/3 for corner neighbours
+// (radial), scale = C/(lam h)^2 with C = 1 (axis) or 2d/(3^d - 1) (radial).
+// Differences are taken before summing, per neighbour class.
+template <typename T, int DIM, int RAD, int SIG>
+__device__ __forceinline__ void stencil(const T *__restrict__ u, const T *__restrict__ sig, int i,
+                                        int j, int k, int m, T scale, T a, T &Lu, T &D)
+{
+    const size_t c = lin(i, j, k, m);
+    const T uc = u[c];
+    const T sc = SIG ? sig[c] : T(1);
+    T acc[3] = {T(0), T(0), T(0)};
+    T ds[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+        const int kk = DIM == 3 ? mir(k + dz, m) : 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int jj = mir(j + dy, m);
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+                if (cls == 0 || (!RAD && cls != 1)) continue;
+                const size_t q = lin(mir(i + dx, m), jj, kk, m);
+                const T du = u[q] - uc;
+                if (SIG) {
+                    const T t = sig[q] + sc;
+                    acc[cls - 1] += t * du;
+                    ds[cls - 1] += t;
+                } else {
+                    acc[cls - 1] += du;
+                }
+            }
+        }
+    }
+    const T third = T(1.0 / 3.0);
+    if (SIG) {
+        const T sw = acc[0] + T(0.5) * acc[1] + third * acc[2];
+        const T dw = ds[0] + T(0.5) * ds[1] + third * ds[2];
+        Lu = scale * T(0.5) * sw + a * uc;
+        D = scale * T(0.5) * dw - a;
+    } else {
+        constexpr int n2 = RAD ? (DIM == 3 ? 12 : 4) : 0;
+        constexpr int n3 = (RAD && DIM == 3) ? 8 : 0;
+        const T W = T(2 * DIM) + T(0.5) * T(n2) + third * T(n3);
+        const T sw = acc[0] + T(0.5) * acc[1] + third * acc[2];
+        Lu = scale * sw + a * uc;
+        D = scale * W - a;
+    }
+}
+
+// Full-grid operator in FP64 on a field whose Dirichlet-node values are
+// replaced by G (or 0): used by the residual recurrence.  `val` maps a node
+// to its value.
+template <int DIM, int RAD, int SIG, typename F>
+__device__ __forceinline__ double stencil_full(F val, const double *__restrict__ sig, int i, int j,
+                                               int k, int m, unsigned dir, double scale, double a)
+{
+    const double uc = val(i, j, k);
+    const double sc = SIG ? sig[lin(i, j, k, m)] : 1.0;
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+        const int kk = DIM == 3 ? mir(k + dz, m) : 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int jj = mir(j + dy, m);
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+                if (cls == 0 || (!RAD && cls != 1)) continue;
+                const int ii = mir(i + dx, m);
+                const double du = val(ii, jj, kk) - uc;
+                if (SIG)
+                    acc[cls - 1] += (sig[lin(ii, jj, kk, m)] + sc) * du;
+                else
+                    acc[cls - 1] += du;
+            }
+        }
+    }
+    const double sw = acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2];
+    (void)dir;
+    return (SIG ? 0.5 * scale * sw : scale * sw) + a * uc;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool node_of(int m, int &i, int &j, int &k)
+{
+    i = blockIdx.x * blockDim.x + threadIdx.x;
+    j = blockIdx.y * blockDim.y + threadIdx.y;
+    k = DIM == 3 ? (int)blockIdx.z : 0;
+    return i < m && j < m;
+}
+
+dim3 grid_of(int dim, int m)
+{
+    return dim3((m + BX - 1) / BX, (m + BY - 1) / BY, dim == 3 ? m : 1);
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <typename T>
+__global__ void k_fill(T *p, size_t count, T value)
+{
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; t < count; t += stride) p[t] = value;
+}
+
+// One relaxation (forward-Euler step of eq. (2), Algorithm 2 lines 3-4) of
+// all nodes of a level, Jacobi style: reads ein, writes eout.  Unknowns:
+// e += theta/D (dL e - g).  Dirichlet nodes take the prescribed value G (the
+// variation G - e of Sec. 2) or 0.  pres (optional): max |dL e - g|.
+template <typename T, int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ ein, T *__restrict__ eout,
+                                               const T *__restrict__ g, const T *__restrict__ sig,
+                                               const double *__restrict__ G, Level L,
+                                               unsigned long long *__restrict__ pres)
+{
+    int i, j, k;
+    unsigned long long rb = 0;
+    if (node_of<DIM>(L.m, i, j, k)) {
+        const size_t c = lin(i, j, k, L.m);
+        if (is_dir<DIM>(i, j, k, L.m, L.dir)) {
+            eout[c] = G ? (T)G[lin(i * L.lam, j * L.lam, k * L.lam, L.N)] : T(0);
+        } else {
+            T Lu, D;
+            stencil<T, DIM, RAD, SIG>(ein, sig, i, j, k, L.m, (T)L.scale, (T)L.a, Lu, D);
+            const T r = Lu - g[c];
+            eout[c] = ein[c] + ((T)L.theta / D) * r;
+            rb = dbits((double)r);
+        }
+    }
+    if (pres) block_max(rb, pres);
+}
+
+// Interpolation of the pending variation of level nu (compact, mc nodes per
+// axis) to level nu-1 (mf = 2 mc - 1): the pending variation at a coarse node
+// X is ec(X) - ef_in(2X) (zero stale values on the level's first visit of a
+// cycle); coarse nodes take ec directly, the others add the multilinear
+// (tensor hat) interpolation -- the mean of the 2, 4 or 8 enclosing coarse
+// nodes.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_prolong(const T *__restrict__ ec, const T *__restrict__ efin,
+                                                 T *__restrict__ efout, int mc, int first)
+{
+    const int mf = 2 * mc - 1;
+    int i, j, k;
+    if (!node_of<DIM>(mf, i, j, k)) return;
+    const int ci = i >> 1, cj = j >> 1, ck = k >> 1;
+    const int oi = i & 1, oj = j & 1, ok = DIM == 3 ? (k & 1) : 0;
+    const size_t f = lin(i, j, k, mf);
+    if (!(oi | oj | ok)) {
+        efout[f] = ec[lin(ci, cj, ck, mc)];
+        return;
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c <= (DIM == 3 ? 1 : 0); ++c) {
+        if (c && !ok) continue;
+#pragma unroll
+        for (int b = 0; b <= 1; ++b) {
+            if (b && !oj) continue;
+#pragma unroll
+            for (int a = 0; a <= 1; ++a) {
+                if (a && !oi) continue;
+                const int X = ci + a, Y = cj + b, Z = ck + c;
+                T p = ec[lin(X, Y, Z, mc)];
+                if (!first) p -= efin[lin(2 * X, 2 * Y, 2 * Z, mf)];
+                acc += p;
+            }
+        }
+    }
+    const T w = T(1) / T(1 << (oi + oj + ok));
+    efout[f] = (first ? T(0) : efin[f]) + w * acc;
+}
+
+// Values of level nu-1 at the level-nu nodes (the schedule climbs a level).
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_inject(const T *__restrict__ ef, T *__restrict__ ec, int mc)
+{
+    const int mf = 2 * mc - 1;
+    int i, j, k;
+    if (!node_of<DIM>(mc, i, j, k)) return;
+    ec[lin(i, j, k, mc)] = ef[lin(2 * i, 2 * j, 2 * k, mf)];
+}
+
+// One restriction step, eq. (3) / eq. (4): the coarse node X averages the
+// fine level's 3^d neighbours of 2X with weights hat(p/2) per axis over 2^d;
+// samples outside the grid are images.  Summed in the same order (z, y, x
+// outer to inner) with exactly representable weights.
+template <typename Tin, typename Tout, int DIM>
+__global__ __launch_bounds__(256) void k_restrict(const Tin *__restrict__ fine, Tout *__restrict__ coarse,
+                                                  int mc)
+{
+    using Acc = typename std::conditional<sizeof(Tin) == 8 || sizeof(Tout) == 8, double, float>::type;
+    const int mf = 2 * mc - 1;
+    int i, j, k;
+    if (!node_of<DIM>(mc, i, j, k)) return;
+    Acc acc = Acc(0);
+#pragma unroll
+    for (int r = (DIM == 3 ? -1 : 0); r <= (DIM == 3 ? 1 : 0); ++r) {
+        const int kk = DIM == 3 ? mir(2 * k + r, mf) : 0;
+        const Acc wr = r == 0 ? Acc(1) : Acc(0.5);
+#pragma unroll
+        for (int q = -1; q <= 1; ++q) {
+            const int jj = mir(2 * j + q, mf);
+            const Acc wq = q == 0 ? Acc(1) : Acc(0.5);
+#pragma unroll
+            for (int p = -1; p <= 1; ++p) {
+                const Acc wp = p == 0 ? Acc(1) : Acc(0.5);
+                acc += (wp * wq * wr) * (Acc)fine[lin(mir(2 * i + p, mf), jj, kk, mf)];
+            }
+        }
+    }
+    coarse[lin(i, j, k, mc)] = (Tout)(acc / Acc(1 << DIM));
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, size_t count)
+{
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; t < count; t += stride) out[t] = (Tout)in[t];
+}
+
+// End of a cycle (recurrence of Sec. 2), FP64 on the full grid:
+//   e = escale * E (E at Dirichlet nodes replaced by G in the first cycle, 0
+//   after), u += e, and at unknowns s -= dL_1 e; s = 0 at Dirichlet nodes.
+//   norm: max |s| over unknowns.  shat (optional): next cycle's source,
+//   shat = (T)(s * shat_scale).
+template <typename T, int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(256) void k_boundary(const T *__restrict__ E, double escale,
+                                                  const double *__restrict__ G,
+                                                  const double *__restrict__ sigma, double *__restrict__ u,
+                                                  double *__restrict__ s, T *__restrict__ shat,
+                                                  double shat_scale, Level L,
+                                                  unsigned long long *__restrict__ norm)
+{
+    int i, j, k;
+    unsigned long long rb = 0;
+    const int m = L.m;
+    if (node_of<DIM>(m, i, j, k)) {
+        const size_t c = lin(i, j, k, m);
+        auto val = [&](int a, int b, int d) -> double {
+            if (is_dir<DIM>(a, b, d, m, L.dir)) return G ? G[lin(a, b, d, m)] : 0.0;
+            return escale * (double)E[lin(a, b, d, m)];
+        };
+        if (is_dir<DIM>(i, j, k, m, L.dir)) {
+            if (G) u[c] += G[c];
+            s[c] = 0.0;
+            if (shat) shat[c] = T(0);
+        } else {
+            const double Le = stencil_full<DIM, RAD, SIG>(val, sigma, i, j, k, m, L.dir, L.scale, L.a);
+            const double sn = s[c] - Le;
+            u[c] += escale * (double)E[c];
+            s[c] = sn;
+            if (shat) shat[c] = (T)(sn * shat_scale);
+            rb = dbits(sn);
+        }
+    }
+    block_max(rb, norm);
+}
+
+// Start of a solve: u = 0, s = f at unknowns (0 at Dirichlet nodes), and
+// norm0 = max |f - dL_1 u_init| with u_init = G on Dirichlet nodes, 0 else.
+template <int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(256) void k_init(const double *__restrict__ f, const double *__restrict__ G,
+                                              const double *__restrict__ sigma, double *__restrict__ s,
+                                              double *__restrict__ u, Level L,
+                                              unsigned long long *__restrict__ norm0)
+{
+    int i, j, k;
+    unsigned long long rb = 0;
+    const int m = L.m;
+    if (node_of<DIM>(m, i, j, k)) {
+        const size_t c = lin(i, j, k, m);
+        u[c] = 0.0;
+        if (is_dir<DIM>(i, j, k, m, L.dir)) {
+            s[c] = 0.0;
+        } else {
+            auto val = [&](int a, int b, int d) -> double {
+                return (G && is_dir<DIM>(a, b, d, m, L.dir)) ? G[lin(a, b, d, m)] : 0.0;
+            };
+            const double Lb = stencil_full<DIM, RAD, SIG>(val, sigma, i, j, k, m, L.dir, L.scale, L.a);
+            s[c] = f[c];
+            rb = dbits(f[c] - Lb);
+        }
+    }
+    block_max(rb, norm0);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_source_cast(const double *__restrict__ s, T *__restrict__ shat,
+                                                     double scale, int m)
+{
+    int i, j, k;
+    if (!node_of<DIM>(m, i, j, k)) return;
+    const size_t c = lin(i, j, k, m);
+    shat[c] = (T)(s[c] * scale);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_set_dirichlet(const double *__restrict__ G, double *__restrict__ u,
+                                                       Level L)
+{
+    int i, j, k;
+    if (!node_of<DIM>(L.m, i, j, k)) return;
+    if (is_dir<DIM>(i, j, k, L.m, L.dir)) {
+        const size_t c = lin(i, j, k, L.m);
+        u[c] = G ? G[c] : 0.0;
+    }
+}
+
+// r = f - dL_1 u at unknowns (0 at Dirichlet nodes); rmax = max |r|;
+// norm0 as in k_init.
+template <int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ f, const double *__restrict__ G,
+                                                  const double *__restrict__ sigma,
+                                                  const double *__restrict__ u, double *__restrict__ r,
+                                                  Level L, unsigned long long *__restrict__ rmax,
+                                                  unsigned long long *__restrict__ norm0)
+{
+    int i, j, k;
+    unsigned long long rb = 0, nb = 0;
+    const int m = L.m;
+    if (node_of<DIM>(m, i, j, k)) {
+        const size_t c = lin(i, j, k, m);
+        if (is_dir<DIM>(i, j, k, m, L.dir)) {
+            if (r) r[c] = 0.0;
+        } else {
+            auto val = [&](int a, int b, int d) -> double { return u[lin(a, b, d, m)]; };
+            auto val0 = [&](int a, int b, int d) -> double {
+                return (G && is_dir<DIM>(a, b, d, m, L.dir)) ? G[lin(a, b, d, m)] : 0.0;
+            };
+            const double rr = f[c] - stencil_full<DIM, RAD, SIG>(val, sigma, i, j, k, m, L.dir, L.scale, L.a);
+            const double r0 = f[c] - stencil_full<DIM, RAD, SIG>(val0, sigma, i, j, k, m, L.dir, L.scale, L.a);
+            if (r) r[c] = rr;
+            rb = dbits(rr);
+            nb = dbits(r0);
+        }
+    }
+    block_max(rb, rmax);
+    block_max(nb, norm0);
+}
+
+// dLoss/dsigma_m = -scale/2 sum_k w_k (u_k - u_m)(lam_m - lam_k), in-grid
+// neighbours only (all faces Dirichlet).
+template <int DIM, int RAD>
+__global__ __launch_bounds__(256) void k_coeff_grad(const double *__restrict__ u,
+                                                    const double *__restrict__ lam,
+                                                    double *__restrict__ grad, Level L)
+{
+    int i, j, k;
+    const int m = L.m;
+    if (!node_of<DIM>(m, i, j, k)) return;
+    const size_t c = lin(i, j, k, m);
+    const double uc = u[c], lc = lam[c];
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+                if (cls == 0 || (!RAD && cls != 1)) continue;
+                const int ii = i + dx, jj = j + dy, kk = k + dz;
+                if (ii < 0 || ii >= m || jj < 0 || jj >= m) continue;
+                if (DIM == 3 && (kk < 0 || kk >= m)) continue;
+                const size_t q = lin(ii, jj, DIM == 3 ? kk : 0, m);
+                acc[cls - 1] += (u[q] - uc) * (lc - lam[q]);
+            }
+        }
+    }
+    grad[c] = -0.5 * L.scale * (acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2]);
+}
+
+// ----------------------------------------------------------- dispatch glue
+
+template <template <int, int, int> class K, typename... A>
+void dispatch3(const Variant &v, A &&...args)
+{
+#define SGML_CASE(D, R, S)                                  \
+    if (v.dim == D && v.radial == R && v.sigma == S) {      \
+        K<D, R, S>::run(std::forward<A>(args)...);          \
+        return;                                             \
+    }
+    SGML_CASE(2, 0, 0) SGML_CASE(2, 0, 1) SGML_CASE(2, 1, 0) SGML_CASE(2, 1, 1)
+    SGML_CASE(3, 0, 0) SGML_CASE(3, 0, 1) SGML_CASE(3, 1, 0) SGML_CASE(3, 1, 1)
+#undef SGML_CASE
+}
+
+dim3 block_of() { return dim3(BX, BY, 1); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+void launch_fill(T *p, size_t count, T value, hipStream_t st)
+{
+    if (count == 0) return;
+    unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, st, p, count, value);
+}
+
+namespace {
+template <typename T>
+struct SweepRun {
+    template <int D, int R, int S>
+    struct K {
+        static void run(const Level &L, const T *ein, T *eout, const T *g, const T *sig, const double *G,
+                        unsigned long long *pres, hipStream_t st)
+        {
+            hipLaunchKernelGGL((k_sweep<T, D, R, S>), grid_of(D, L.m), block_of(), 0, st, ein, eout, g, sig,
+                               G, L, pres);
+        }
+    };
+};
+}  // namespace
+
+template <typename T>
+void launch_sweep(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
+                  const double *G, unsigned long long *pres, hipStream_t st)
+{
+    dispatch3<SweepRun<T>::template K>(v, L, ein, eout, g, sig, G, pres, st);
+}
+
+template <typename T>
+void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)
+{
+    const int mf = 2 * mc - 1;
+    if (dim == 2)
+        hipLaunchKernelGGL((k_prolong<T, 2>), grid_of(2, mf), block_of(), 0, st, ec, ef_in, ef_out, mc,
+                           (int)first);
+    else
+        hipLaunchKernelGGL((k_prolong<T, 3>), grid_of(3, mf), block_of(), 0, st, ec, ef_in, ef_out, mc,
+                           (int)first);
+}
+
+template <typename T>
+void launch_inject(int dim, int mc, const T *ef, T *ec, hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_inject<T, 2>), grid_of(2, mc), block_of(), 0, st, ef, ec, mc);
+    else
+        hipLaunchKernelGGL((k_inject<T, 3>), grid_of(3, mc), block_of(), 0, st, ef, ec, mc);
+}
+
+template <typename Tin, typename Tout>
+void launch_restrict(int dim, int mc, const Tin *fine, Tout *coarse, hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_restrict<Tin, Tout, 2>), grid_of(2, mc), block_of(), 0, st, fine, coarse, mc);
+    else
+        hipLaunchKernelGGL((k_restrict<Tin, Tout, 3>), grid_of(3, mc), block_of(), 0, st, fine, coarse, mc);
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *in, Tout *out, size_t count, hipStream_t st)
+{
+    if (count == 0) return;
+    unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(blocks), dim3(256), 0, st, in, out, count);
+}
+
+namespace {
+template <typename T>
+struct BoundaryRun {
+    template <int D, int R, int S>
+    struct K {
+        static void run(const Level &L, const T *e, double escale, const double *G, const double *sigma,
+                        double *u, double *s, T *shat, double shat_scale, unsigned long long *norm,
+                        hipStream_t st)
+        {
+            hipLaunchKernelGGL((k_boundary<T, D, R, S>), grid_of(D, L.m), block_of(), 0, st, e, escale, G,
+                               sigma, u, s, shat, shat_scale, L, norm);
+        }
+    };
+};
+template <int D, int R, int S>
+struct InitRun {
+    static void run(const Level &L, const double *f, const double *G, const double *sigma, double *s,
+                    double *u, unsigned long long *norm0, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_init<D, R, S>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, s, u, L,
+                           norm0);
+    }
+};
+template <int D, int R, int S>
+struct ResidualRun {
+    static void run(const Level &L, const double *f, const double *G, const double *sigma,
+                    const double *u, double *r, unsigned long long *rmax, unsigned long long *norm0,
+                    hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_residual<D, R, S>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, u, r,
+                           L, rmax, norm0);
+    }
+};
+}  // namespace
+
+template <typename T>
+void launch_boundary(const Variant &v, const Level &L, const T *e, double escale, const double *G,
+                     const double *sigma, double *u, double *s, T *shat, double shat_scale,
+                     unsigned long long *norm, hipStream_t st)
+{
+    dispatch3<BoundaryRun<T>::template K>(v, L, e, escale, G, sigma, u, s, shat, shat_scale, norm, st);
+}
+
+void launch_init(const Variant &v, const Level &L, const double *f, const double *G, const double *sigma,
+                 double *s, double *u, unsigned long long *norm0, hipStream_t st)
+{
+    dispatch3<InitRun>(v, L, f, G, sigma, s, u, norm0, st);
+}
+
+template <typename T>
+void launch_source_cast(const Level &L, int dim, const double *s, T *shat, double scale, hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_source_cast<T, 2>), grid_of(2, L.m), block_of(), 0, st, s, shat, scale, L.m);
+    else
+        hipLaunchKernelGGL((k_source_cast<T, 3>), grid_of(3, L.m), block_of(), 0, st, s, shat, scale, L.m);
+}
+
+void launch_set_dirichlet(const Level &L, int dim, const double *G, double *u, hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_set_dirichlet<2>), grid_of(2, L.m), block_of(), 0, st, G, u, L);
+    else
+        hipLaunchKernelGGL((k_set_dirichlet<3>), grid_of(3, L.m), block_of(), 0, st, G, u, L);
+}
+
+void launch_residual(const Variant &v, const Level &L, const double *f, const double *G,
+                     const double *sigma, const double *u, double *r, unsigned long long *rmax,
+                     unsigned long long *norm0, hipStream_t st)
+{
+    dispatch3<ResidualRun>(v, L, f, G, sigma, u, r, rmax, norm0, st);
+}
+
+void launch_coeff_grad(const Variant &v, const Level &L, const double *u, const double *lam, double *grad,
+                       hipStream_t st)
+{
+    if (v.dim == 2 && !v.radial)
+        hipLaunchKernelGGL((k_coeff_grad<2, 0>), grid_of(2, L.m), block_of(), 0, st, u, lam, grad, L);
+    else if (v.dim == 2)
+        hipLaunchKernelGGL((k_coeff_grad<2, 1>), grid_of(2, L.m), block_of(), 0, st, u, lam, grad, L);
+    else if (!v.radial)
+        hipLaunchKernelGGL((k_coeff_grad<3, 0>), grid_of(3, L.m), block_of(), 0, st, u, lam, grad, L);
+    else
+        hipLaunchKernelGGL((k_coeff_grad<3, 1>), grid_of(3, L.m), block_of(), 0, st, u, lam, grad, L);
+}
+
+// explicit instantiations
+template void launch_fill<double>(double *, size_t, double, hipStream_t);
+template void launch_fill<float>(float *, size_t, float, hipStream_t);
+template void launch_fill<unsigned long long>(unsigned long long *, size_t, unsigned long long, hipStream_t);
+template void launch_sweep<double>(const Variant &, const Level &, const double *, double *, const double *,
+                                   const double *, const double *, unsigned long long *, hipStream_t);
+template void launch_sweep<float>(const Variant &, const Level &, const float *, float *, const float *,
+                                  const float *, const double *, unsigned long long *, hipStream_t);
+template void launch_prolong<double>(int, int, const double *, const double *, double *, bool, hipStream_t);
+template void launch_prolong<float>(int, int, const float *, const float *, float *, bool, hipStream_t);
+template void launch_inject<double>(int, int, const double *, double *, hipStream_t);
+template void launch_inject<float>(int, int, const float *, float *, hipStream_t);
+template void launch_restrict<double, double>(int, int, const double *, double *, hipStream_t);
+template void launch_restrict<float, float>(int, int, const float *, float *, hipStream_t);
+template void launch_restrict<double, float>(int, int, const double *, float *, hipStream_t);
+template void launch_convert<double, float>(const double *, float *, size_t, hipStream_t);
+template void launch_boundary<double>(const Variant &, const Level &, const double *, double, const double *,
+                                      const double *, double *, double *, double *, double,
+                                      unsigned long long *, hipStream_t);
+template void launch_boundary<float>(const Variant &, const Level &, const float *, double, const double *,
+                                     const double *, double *, double *, float *, double,
+                                     unsigned long long *, hipStream_t);
+template void launch_source_cast<float>(const Level &, int, const double *, float *, double, hipStream_t);
+template void launch_source_cast<double>(const Level &, int, const double *, double *, double, hipStream_t);
+
+}  // namespace sgml

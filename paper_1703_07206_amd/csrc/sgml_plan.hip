@@ -1,0 +1,572 @@
+// sgml_plan.hip -- host side of the SGML library: the C-ABI of
+// include/sgml.h, the workspace layout, the visit schedule (Algorithm 3) and
+// the residual recurrence with its stop test (Sec. 2, Sec. 3.1).
+#include "sgml.h"
+#include "sgml_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+using namespace sgml;
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr size_t kAlign = 256;
+// reduction targets: [0] residual norm, [1] norm0, [2] rmax, [kPres + v] pseudo-residual of visit v
+constexpr int kPres = 4;
+constexpr int kTargets = kPres + SGML_MAX_VISITS;
+constexpr size_t kScalars = (size_t)kTargets * kRedWords;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t scal, s, e0, shat, sig0t;
+    size_t e[kMaxLevels][2], g[kMaxLevels], sig64[kMaxLevels], sigt[kMaxLevels];
+    size_t total;
+};
+
+bool valid_problem(const sgml_problem *p)
+{
+    if (!p) return false;
+    if (p->dim != 2 && p->dim != 3) return false;
+    if (p->stencil != SGML_AXIS && p->stencil != SGML_RADIAL) return false;
+    for (int f = 0; f < 2 * p->dim; ++f)
+        if (p->face[f] != SGML_DIRICHLET && p->face[f] != SGML_NEUMANN) return false;
+    if (!std::isfinite(p->a) || !std::isfinite(p->theta)) return false;
+    return true;
+}
+
+bool valid_shape(const sgml_problem *p)
+{
+    return p->n >= 2 && p->n <= (p->dim == 2 ? 13 : 10);
+}
+
+size_t level_nodes(int dim, int n, int nu)
+{
+    size_t m = ((size_t)1 << (n - nu)) + 1;
+    return dim == 3 ? m * m * m : m * m;
+}
+
+Layout make_layout(const sgml_problem *p, int precision)
+{
+    Layout L;
+    std::memset(&L, 0, sizeof(L));
+    const bool mixed = precision == SGML_MIXED;
+    const size_t M = level_nodes(p->dim, p->n, 0);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.scal = take(sizeof(unsigned long long) * kScalars);
+    L.s = take(8 * M);
+    L.e0 = take(2 * 8 * M);  // two level-0 buffers, FP64-sized (FP32 uses half)
+    L.shat = mixed ? take(4 * M) : 0;
+    L.sig0t = mixed ? take(4 * M) : 0;
+    for (int nu = 1; nu < p->n; ++nu) {
+        const size_t c = level_nodes(p->dim, p->n, nu);
+        L.e[nu][0] = take(8 * c);
+        L.e[nu][1] = take(8 * c);
+        L.g[nu] = take(8 * c);
+        L.sig64[nu] = take(8 * c);
+        L.sigt[nu] = mixed ? take(4 * c) : 0;
+    }
+    L.total = off;
+    return L;
+}
+
+// Algorithm 3 as a visit list.  Tooth nu1 = n-1 .. 0 visits nu1, nu1 - 1
+// (not below 0) and nu1 again, each min(n_r, 2^(n - nu1)) times; the
+// level-0 relaxations of lines 9-10 (min(n_r, 2^n) times) close the cycle
+// once (SGML_SCHEDULE_ONCE) or every tooth (SGML_SCHEDULE_EACH).
+void build_schedule(int n, int n_r, int sched, std::vector<int> &lev, std::vector<int> &cnt)
+{
+    lev.clear();
+    cnt.clear();
+    auto cap = [&](long long full) { return (int)((n_r > 0 && n_r < full) ? n_r : full); };
+    for (int nu1 = n - 1; nu1 >= 0; --nu1) {
+        const int c = cap(1LL << (n - nu1));
+        const int tooth[3] = {nu1, nu1 - 1, nu1};
+        for (int t = 0; t < 3; ++t) {
+            if (tooth[t] < 0) continue;
+            lev.push_back(tooth[t]);
+            cnt.push_back(c);
+        }
+        if (sched == SGML_SCHEDULE_EACH) {
+            lev.push_back(0);
+            cnt.push_back(cap(1LL << n));
+        }
+    }
+    if (sched != SGML_SCHEDULE_EACH) {
+        lev.push_back(0);
+        cnt.push_back(cap(1LL << n));
+    }
+}
+
+double default_theta(int dim, int stencil)
+{
+    if (stencil == SGML_RADIAL) return 1.0;
+    return dim == 2 ? 0.8 : 6.0 / 7.0;
+}
+
+}  // namespace
+
+struct sgml_plan {
+    sgml_problem prob;
+    int precision;
+    int dim, n, N;
+    size_t M;
+    double h, C, theta;
+    unsigned dir;
+    Variant var;
+    char *ws;
+    size_t ws_bytes;
+    Layout lay;
+    const double *sigma;
+    int device;
+    unsigned long long *host;  // pinned copy of the reduction targets (kScalars words)
+    hipEvent_t ev0, ev1;
+    std::vector<hipEvent_t> pev;  // profiling events, pairs around timed launches
+    size_t pev_used = 0;
+
+    template <typename T>
+    T *at(size_t off) const
+    {
+        return reinterpret_cast<T *>(ws + off);
+    }
+    int m(int nu) const { return (1 << (n - nu)) + 1; }
+    Level level(int nu) const
+    {
+        Level L;
+        L.m = m(nu);
+        L.lam = 1 << nu;
+        L.N = N;
+        L.dir = dir;
+        const double lh = L.lam * h;
+        L.scale = C / (lh * lh);
+        L.a = prob.a;
+        L.theta = theta;
+        return L;
+    }
+};
+
+#define SGML_HIP(call)                                  \
+    do {                                                \
+        if ((call) != hipSuccess) return SGML_E_HIP;    \
+    } while (0)
+
+namespace {
+
+unsigned long long *target(sgml_plan *P, int t)
+{
+    return P->at<unsigned long long>(P->lay.scal) + (size_t)t * kRedWords;
+}
+
+// Copy reduction targets [first, first + count) to the pinned host block.
+sgml_status fetch(sgml_plan *P, int first, int count, hipStream_t st)
+{
+    SGML_HIP(hipMemcpyAsync(P->host + (size_t)first * kRedWords, target(P, first),
+                            sizeof(unsigned long long) * kRedWords * count, hipMemcpyDeviceToHost, st));
+    SGML_HIP(hipStreamSynchronize(st));
+    return SGML_OK;
+}
+
+void clear_targets(sgml_plan *P, int first, int count, hipStream_t st)
+{
+    launch_fill<unsigned long long>(target(P, first), (size_t)kRedWords * count, 0ull, st);
+}
+
+double as_double(unsigned long long b);
+
+// max over the slots of a fetched target
+double host_max(const sgml_plan *P, int t)
+{
+    unsigned long long m = 0;
+    for (int s = 0; s < kRedSlots; ++s) {
+        const unsigned long long v = P->host[(size_t)t * kRedWords + (size_t)s * kRedStride];
+        m = v > m ? v : m;
+    }
+    return as_double(m);
+}
+
+// Profiling: a pair of events around a launch; drained once per cycle.
+hipEvent_t *prof_pair(sgml_plan *P)
+{
+    if (P->pev_used + 2 > P->pev.size()) {
+        for (int t = 0; t < 64; ++t) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            P->pev.push_back(e);
+        }
+    }
+    hipEvent_t *pr = &P->pev[P->pev_used];
+    P->pev_used += 2;
+    return pr;
+}
+
+double as_double(unsigned long long b)
+{
+    double d;
+    std::memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+// One cycle of Algorithm 3 from e = 0 on the level-0 source src0, in T.
+// Returns the level-0 buffer holding the cycle's e.
+template <typename T>
+const T *run_cycle(sgml_plan *P, const T *src0, const double *G, const std::vector<int> &lev,
+                   const std::vector<int> &cnt, bool record, bool profile,
+                   std::vector<std::pair<int, hipEvent_t *>> &timed, long long &updates, hipStream_t st)
+{
+    const int n = P->n, dim = P->dim;
+    const bool mixed = sizeof(T) == 4;
+    T *E[kMaxLevels][2];
+    const T *g[kMaxLevels];
+    const T *sig[kMaxLevels];
+    E[0][0] = P->at<T>(P->lay.e0);
+    E[0][1] = E[0][0] + P->M;
+    g[0] = src0;
+    sig[0] = P->var.sigma ? (mixed ? (const T *)P->at<T>(P->lay.sig0t) : (const T *)P->sigma) : nullptr;
+    for (int nu = 1; nu < n; ++nu) {
+        E[nu][0] = P->at<T>(P->lay.e[nu][0]);
+        E[nu][1] = P->at<T>(P->lay.e[nu][1]);
+        T *gn = P->at<T>(P->lay.g[nu]);
+        g[nu] = gn;
+        sig[nu] = P->var.sigma ? (mixed ? (const T *)P->at<T>(P->lay.sigt[nu])
+                                        : (const T *)P->at<T>(P->lay.sig64[nu]))
+                               : nullptr;
+        // restriction(nu) of the cycle source (Algorithm 1), kept for the cycle
+        launch_restrict<T, T>(dim, P->m(nu), g[nu - 1], gn, st);
+    }
+    int cur[kMaxLevels] = {0};
+    bool seen[kMaxLevels] = {false};
+    int prev = -1;
+    for (size_t v = 0; v < lev.size(); ++v) {
+        const int nu = lev[v];
+        if (prev < 0) {
+            launch_fill<T>(E[nu][cur[nu]], level_nodes(dim, n, nu), T(0), st);
+        }
+        // walk one level at a time: refining interpolates the pending
+        // variation into the finer level, coarsening copies the finer values
+        while (prev > nu) {
+            const int f = prev - 1;
+            launch_prolong<T>(dim, P->m(prev), E[prev][cur[prev]], E[f][cur[f]], E[f][cur[f] ^ 1],
+                              !seen[f], st);
+            cur[f] ^= 1;
+            seen[f] = true;
+            prev = f;
+        }
+        while (prev >= 0 && prev < nu) {
+            const int c = prev + 1;
+            launch_inject<T>(dim, P->m(c), E[prev][cur[prev]], E[c][cur[c]], st);
+            seen[c] = true;
+            prev = c;
+        }
+        seen[nu] = true;
+        const Level L = P->level(nu);
+        for (int r = 0; r < cnt[v]; ++r) {
+            unsigned long long *pr = (record && r == cnt[v] - 1) ? target(P, kPres + (int)v) : nullptr;
+            hipEvent_t *ev = (profile && nu == 0) ? prof_pair(P) : nullptr;
+            if (ev) (void)hipEventRecord(ev[0], st);
+            launch_sweep<T>(P->var, L, E[nu][cur[nu]], E[nu][cur[nu] ^ 1], g[nu], sig[nu], G, pr, st);
+            if (ev) {
+                (void)hipEventRecord(ev[1], st);
+                timed.emplace_back(0, ev);
+            }
+            cur[nu] ^= 1;
+        }
+        updates += (long long)cnt[v] * (long long)level_nodes(dim, n, nu);
+        prev = nu;
+    }
+    return E[0][cur[0]];
+}
+
+template <typename T>
+sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u, const sgml_opts *o,
+                      hipStream_t st, sgml_stats *stats)
+{
+    const bool mixed = sizeof(T) == 4;
+    const Level L0 = P->level(0);
+    double *s = P->at<double>(P->lay.s);
+    T *shat = mixed ? P->at<T>(P->lay.shat) : nullptr;
+    const T *src0 = mixed ? shat : (const T *)s;
+    std::vector<int> lev, cnt;
+    build_schedule(P->n, o->n_r, o->schedule, lev, cnt);
+    if ((int)lev.size() > SGML_MAX_VISITS) return SGML_E_ARG;
+
+    sgml_stats local;
+    sgml_stats &S = stats ? *stats : local;
+    std::memset(&S, 0, sizeof(S));
+    S.visits = (int)lev.size();
+
+    SGML_HIP(hipEventRecord(P->ev0, st));
+    clear_targets(P, 1, 1, st);
+    launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), st);
+    SGML_HIP(hipGetLastError());
+    sgml_status rc = fetch(P, 1, 1, st);
+    if (rc != SGML_OK) return rc;
+    const double norm0 = host_max(P, 1);
+    S.norm0 = norm0;
+    sgml_status status = SGML_E_MAXCYCLES;
+    if (!(norm0 > 0.0)) {
+        // u_init = G on Dirichlet nodes, 0 elsewhere, already solves the problem
+        launch_set_dirichlet(L0, P->dim, G, u, st);
+        status = std::isfinite(norm0) ? SGML_OK : SGML_E_ARG;
+    } else {
+        int k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
+        if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
+        double last = norm0;
+        for (int i = 0; i < o->max_cycles; ++i) {
+            const double *Gc = i == 0 ? G : nullptr;
+            clear_targets(P, 0, 1, st);
+            if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
+            std::vector<std::pair<int, hipEvent_t *>> timed;
+            P->pev_used = 0;
+            const T *e = run_cycle<T>(P, src0, Gc, lev, cnt, o->record_pres != 0, o->profile != 0, timed,
+                                      S.node_updates, st);
+            // next cycle's scaling from the last known residual norm (lagged)
+            const int k_next = mixed ? std::ilogb(last) : 0;
+            hipEvent_t *ev = o->profile ? prof_pair(P) : nullptr;
+            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
+                               std::ldexp(1.0, -k_next), target(P, 0), st);
+            if (ev) {
+                SGML_HIP(hipEventRecord(ev[1], st));
+                timed.emplace_back(1, ev);
+            }
+            SGML_HIP(hipGetLastError());
+            rc = fetch(P, 0, 1, st);
+            if (rc != SGML_OK) return rc;
+            for (auto &t : timed) {
+                float ms = 0.f;
+                SGML_HIP(hipEventElapsedTime(&ms, t.second[0], t.second[1]));
+                if (t.first == 0) {
+                    S.sweep0_ms += ms;
+                    S.sweep0_launches++;
+                } else {
+                    S.boundary_ms += ms;
+                    S.boundary_launches++;
+                }
+            }
+            const double norm = host_max(P, 0);
+            const double rel = norm / norm0;
+            S.cycles = i + 1;
+            S.relres = rel;
+            if (i < SGML_HIST) S.history[i] = rel;
+            k_cur = k_next;
+            last = norm;
+            if (!std::isfinite(rel) || rel > 1e3) {
+                status = SGML_E_DIVERGED;
+                break;
+            }
+            if (rel <= o->tol) {
+                status = SGML_OK;
+                break;
+            }
+            if (i >= 3 && i - 3 < SGML_HIST && rel > 0.5 * S.history[i - 3]) {
+                status = SGML_E_STAGNATED;
+                break;
+            }
+        }
+        if (o->record_pres) {
+            rc = fetch(P, kPres, (int)lev.size(), st);
+            if (rc != SGML_OK) return rc;
+            for (size_t v = 0; v < lev.size(); ++v) S.pres[v] = host_max(P, kPres + (int)v);
+        }
+    }
+    SGML_HIP(hipEventRecord(P->ev1, st));
+    SGML_HIP(hipEventSynchronize(P->ev1));
+    SGML_HIP(hipEventElapsedTime(&S.ms, P->ev0, P->ev1));
+    S.status = status;
+    return status;
+}
+
+bool all_dirichlet(const sgml_plan *P)
+{
+    for (int f = 0; f < 2 * P->dim; ++f)
+        if (P->prob.face[f] != SGML_DIRICHLET) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sgml_workspace_bytes(const sgml_problem *prob, int precision)
+{
+    if (!valid_problem(prob) || !valid_shape(prob)) return 0;
+    if (precision != SGML_FP64 && precision != SGML_MIXED) return 0;
+    return make_layout(prob, precision).total;
+}
+
+sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *workspace, size_t ws_bytes,
+                             sgml_plan **out)
+{
+    if (!out) return SGML_E_ARG;
+    *out = nullptr;
+    if (!valid_problem(prob)) return SGML_E_ARG;
+    if (precision != SGML_FP64 && precision != SGML_MIXED) return SGML_E_ARG;
+    if (!valid_shape(prob)) return SGML_E_SHAPE;
+    const Layout lay = make_layout(prob, precision);
+    if (!workspace || ws_bytes < lay.total || ((uintptr_t)workspace % kAlign) != 0) return SGML_E_WORKSPACE;
+    sgml_plan *P = new (std::nothrow) sgml_plan();
+    if (!P) return SGML_E_ARG;
+    P->prob = *prob;
+    P->precision = precision;
+    P->dim = prob->dim;
+    P->n = prob->n;
+    P->N = (1 << prob->n) + 1;
+    P->M = level_nodes(prob->dim, prob->n, 0);
+    P->h = 1.0 / (double)(1 << prob->n);
+    const int K = prob->stencil == SGML_RADIAL ? (prob->dim == 3 ? 26 : 8) : 2 * prob->dim;
+    P->C = prob->stencil == SGML_RADIAL ? (2.0 * prob->dim) / K : 1.0;
+    P->theta = prob->theta > 0.0 ? prob->theta : default_theta(prob->dim, prob->stencil);
+    P->dir = 0;
+    for (int f = 0; f < 2 * prob->dim; ++f)
+        if (prob->face[f] == SGML_DIRICHLET) P->dir |= 1u << f;
+    P->var.dim = prob->dim;
+    P->var.radial = prob->stencil == SGML_RADIAL;
+    P->var.sigma = 0;
+    P->ws = static_cast<char *>(workspace);
+    P->ws_bytes = ws_bytes;
+    P->lay = lay;
+    P->sigma = nullptr;
+    if (hipGetDevice(&P->device) != hipSuccess ||
+        hipHostMalloc((void **)&P->host, sizeof(unsigned long long) * kScalars, hipHostMallocDefault) !=
+            hipSuccess) {
+        delete P;
+        return SGML_E_HIP;
+    }
+    if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) {
+        (void)hipHostFree(P->host);
+        delete P;
+        return SGML_E_HIP;
+    }
+    *out = P;
+    return SGML_OK;
+}
+
+sgml_status sgml_plan_set_coeffs(sgml_plan *P, const double *sigma, void *stream)
+{
+    if (!P) return SGML_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    SGML_HIP(hipSetDevice(P->device));
+    P->sigma = sigma;
+    P->var.sigma = sigma ? 1 : 0;
+    if (!sigma) return SGML_OK;
+    // restricted coefficients per level: Algorithm 1 applied to sigma
+    const double *prev = sigma;
+    for (int nu = 1; nu < P->n; ++nu) {
+        double *cur = P->at<double>(P->lay.sig64[nu]);
+        launch_restrict<double, double>(P->dim, P->m(nu), prev, cur, st);
+        prev = cur;
+    }
+    if (P->precision == SGML_MIXED) {
+        launch_convert<double, float>(sigma, P->at<float>(P->lay.sig0t), P->M, st);
+        for (int nu = 1; nu < P->n; ++nu)
+            launch_convert<double, float>(P->at<double>(P->lay.sig64[nu]), P->at<float>(P->lay.sigt[nu]),
+                                          level_nodes(P->dim, P->n, nu), st);
+    }
+    SGML_HIP(hipGetLastError());
+    return SGML_OK;
+}
+
+sgml_status sgml_solve(sgml_plan *P, const double *f, const double *G, double *u, const sgml_opts *o,
+                       void *stream, sgml_stats *stats)
+{
+    if (!P || !f || !u || !o) return SGML_E_ARG;
+    if (o->max_cycles < 1 || !(o->tol >= 0.0)) return SGML_E_ARG;
+    if (o->precision != SGML_FP64 && o->precision != SGML_MIXED) return SGML_E_ARG;
+    if (o->precision == SGML_MIXED && P->precision != SGML_MIXED) return SGML_E_WORKSPACE;
+    if (o->schedule != SGML_SCHEDULE_ONCE && o->schedule != SGML_SCHEDULE_EACH) return SGML_E_ARG;
+    if (u == f || (G && u == G)) return SGML_E_ARG;
+    SGML_HIP(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    sgml_status rc = o->precision == SGML_MIXED ? run_solve<float>(P, f, G, u, o, st, stats)
+                                                : run_solve<double>(P, f, G, u, o, st, stats);
+    if (stats) stats->status = rc;
+    return rc;
+}
+
+sgml_status sgml_residual(sgml_plan *P, const double *f, const double *G, const double *u, double *r,
+                          double *rmax, double *norm0, void *stream)
+{
+    if (!P || !f || !u) return SGML_E_ARG;
+    SGML_HIP(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    clear_targets(P, 1, 2, st);
+    launch_residual(P->var, P->level(0), f, G, P->sigma, u, r, target(P, 2), target(P, 1), st);
+    SGML_HIP(hipGetLastError());
+    sgml_status rc = fetch(P, 1, 2, st);
+    if (rc != SGML_OK) return rc;
+    if (norm0) *norm0 = host_max(P, 1);
+    if (rmax) *rmax = host_max(P, 2);
+    return SGML_OK;
+}
+
+sgml_status sgml_adjoint(sgml_plan *P, const double *g, double *lambda, const sgml_opts *o, void *stream,
+                         sgml_stats *stats)
+{
+    if (!P) return SGML_E_ARG;
+    if (!all_dirichlet(P)) return SGML_E_UNSUPPORTED;
+    // symmetric operator: the transposed solve is the solve itself, with the
+    // adjoint vanishing on Dirichlet nodes
+    return sgml_solve(P, g, nullptr, lambda, o, stream, stats);
+}
+
+sgml_status sgml_coeff_grad(sgml_plan *P, const double *u, const double *lambda, double *grad, void *stream)
+{
+    if (!P || !u || !lambda || !grad) return SGML_E_ARG;
+    if (!all_dirichlet(P)) return SGML_E_UNSUPPORTED;
+    SGML_HIP(hipSetDevice(P->device));
+    launch_coeff_grad(P->var, P->level(0), u, lambda, grad, (hipStream_t)stream);
+    SGML_HIP(hipGetLastError());
+    return SGML_OK;
+}
+
+sgml_status sgml_schedule(int n, int n_r, int schedule, int *level, int *count, int cap, int *len)
+{
+    if (n < 1 || n > 30 || !len || cap < 0 || (cap > 0 && (!level || !count))) return SGML_E_ARG;
+    if (schedule != SGML_SCHEDULE_ONCE && schedule != SGML_SCHEDULE_EACH) return SGML_E_ARG;
+    std::vector<int> lev, cnt;
+    build_schedule(n, n_r, schedule, lev, cnt);
+    for (int v = 0; v < (int)lev.size() && v < cap; ++v) {
+        level[v] = lev[v];
+        count[v] = cnt[v];
+    }
+    *len = (int)lev.size();
+    return SGML_OK;
+}
+
+const char *sgml_status_string(sgml_status s)
+{
+    switch (s) {
+    case SGML_OK: return "ok";
+    case SGML_E_ARG: return "invalid argument";
+    case SGML_E_SHAPE: return "unsupported grid shape";
+    case SGML_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case SGML_E_HIP: return "HIP runtime error";
+    case SGML_E_DIVERGED: return "diverged";
+    case SGML_E_STAGNATED: return "stagnated";
+    case SGML_E_MAXCYCLES: return "maximum number of cycles reached";
+    case SGML_E_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+void sgml_plan_destroy(sgml_plan *P)
+{
+    if (!P) return;
+    (void)hipEventDestroy(P->ev0);
+    (void)hipEventDestroy(P->ev1);
+    for (hipEvent_t e : P->pev) (void)hipEventDestroy(e);
+    (void)hipHostFree(P->host);
+    delete P;
+}
+
+}  // extern "C"

@@ -47,7 +47,7 @@ typedef enum {
     SGML_E_WORKSPACE = -3,   /* workspace missing, too small or misaligned */
     SGML_E_HIP = -4,         /* a HIP runtime call failed */
     SGML_E_DIVERGED = -5,    /* residual non-finite or grew above 1e3 x initial */
-    SGML_E_STAGNATED = -6,   /* residual fell by less than 2x over 3 cycles */
+    SGML_E_STAGNATED = -6,   /* residual fell by less than 2x over stall_window cycles */
     SGML_E_MAXCYCLES = -7,   /* max_cycles reached above the tolerance */
     SGML_E_UNSUPPORTED = -8  /* valid request outside what this build implements */
 } sgml_status;
@@ -95,10 +95,20 @@ typedef struct {
     int record_pres;  /* 1: keep the per-visit pseudo-residuals of the last cycle */
     int profile;      /* 1: time every level-0 sweep and boundary pass with stream
                          events (sweep0_ms, boundary_ms in the stats) */
+    int coarse_nodes; /* levels of at most this many nodes run together in one
+                         single-workgroup launch per run of coarse operations;
+                         0: default (5000), < 0: every operation launched alone */
+    int stall_window; /* SGML_E_STAGNATED when the residual has not halved over
+                         this many cycles; 0: default (3), < 0: never */
+    int fuse;         /* 2D levels too large for the coarse kernel: 0 (default)
+                         runs each visit as one fused pass, < 0 one launch per
+                         interpolation, relaxation and injection */
 } sgml_opts;
 
 #define SGML_HIST 512
 #define SGML_MAX_VISITS 128
+#define SGML_PROF_CLASSES 4
+enum { SGML_PROF_SWEEP0 = 0, SGML_PROF_VISIT0_INJ = 1, SGML_PROF_VISIT0 = 2, SGML_PROF_CYCLE_END = 3 };
 typedef struct {
     int status;                     /* same value as returned */
     int cycles;                     /* cycles run */
@@ -111,10 +121,14 @@ typedef struct {
                                        relaxation, last cycle (record_pres) */
     long long node_updates;         /* level-node relaxations performed */
     float ms;                       /* device time of the solve, stream events */
-    int sweep0_launches;            /* level-0 relaxation launches (profile) */
-    float sweep0_ms;                /* their summed device time (profile) */
-    int boundary_launches;          /* cycle-end passes (profile) */
-    float boundary_ms;              /* their summed device time (profile) */
+    /* profile: launches, summed device time and relaxations of the level-0
+     * kernels by class: SGML_PROF_SWEEP0 one relaxation per launch;
+     * SGML_PROF_VISIT0_INJ / SGML_PROF_VISIT0 fused visits (interpolation
+     * prologue, several relaxations) with / without the injection epilogue;
+     * SGML_PROF_CYCLE_END the cycle-end pass (residual recurrence) */
+    int prof_launches[SGML_PROF_CLASSES];
+    float prof_ms[SGML_PROF_CLASSES];
+    int prof_sweeps[SGML_PROF_CLASSES];
 } sgml_stats;
 
 typedef struct sgml_plan sgml_plan;

@@ -26,7 +26,7 @@ class Problem(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_cycles", ctypes.c_int), ("n_r", ctypes.c_int),
-                ("reading", ctypes.c_int)]
+                ("reading", ctypes.c_int), ("stall_window", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -136,8 +136,8 @@ class OracleProblem:
 
     # -- cycle / solve --------------------------------------------------
     @staticmethod
-    def _opts(tol=1e-12, max_cycles=100, n_r=2, reading=0):
-        return Opts(tol, max_cycles, n_r, reading)
+    def _opts(tol=1e-12, max_cycles=100, n_r=2, reading=0, stall_window=0):
+        return Opts(tol, max_cycles, n_r, reading, stall_window)
 
     def cycle(self, src, G=None, n_r=2, reading=0, with_pres=False, with_trace=False):
         """One cycle from zero.  Returns e, plus the per-visit pseudo-residuals
@@ -158,12 +158,12 @@ class OracleProblem:
             out += (trace,)
         return out if len(out) > 1 else e
 
-    def solve(self, f, G=None, tol=1e-12, max_cycles=100, n_r=2, reading=0):
+    def solve(self, f, G=None, tol=1e-12, max_cycles=100, n_r=2, reading=0, stall_window=0):
         """Returns (u, info) with info a dict of the solve statistics."""
         f, G = _f64(f), _f64(G)
         u = np.empty(self.shape)
         st = Stats()
-        o = self._opts(tol, max_cycles, n_r, reading)
+        o = self._opts(tol, max_cycles, n_r, reading, stall_window)
         rc = lib().orc_solve(ctypes.byref(self._p), ctypes.byref(o), _ptr(f), _ptr(G), _ptr(u),
                              ctypes.byref(st))
         assert rc != E_ARG

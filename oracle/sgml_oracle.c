@@ -60,6 +60,8 @@ typedef struct {
     int max_cycles;
     int n_r;          /* cap on relaxation-interpolations per visit, <= 0: none */
     int reading;      /* 0: Algorithm 3 lines 9-10 run once after the loop; 1: inside it */
+    int stall_window; /* STAGNATED when the residual has not halved over this many
+                         cycles; 0: 3, < 0: never */
 } orc_opts;
 
 #define ORC_HIST 512
@@ -594,7 +596,7 @@ int orc_cycle(const orc_problem *p, const orc_opts *o, const double *src, const 
  * elsewhere, which is f itself for homogeneous conditions and stays defined
  * when f = 0 (a problem driven by its boundary values).
  * Failure statuses: DIVERGED (non-finite or growth above 1e3),
- * STAGNATED (less than a factor 2 over three cycles), MAXCYCLES. */
+ * STAGNATED (less than a factor 2 over stall_window cycles), MAXCYCLES. */
 int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const double *G, double *u,
               orc_stats *st)
 {
@@ -664,7 +666,8 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
                 status = ORC_OK;
                 break;
             }
-            if (i >= 3 && i - 3 < ORC_HIST && rel > 0.5 * st->history[i - 3]) {
+            const int win = o->stall_window == 0 ? 3 : o->stall_window;
+            if (win > 0 && i >= win && i < ORC_HIST && rel > 0.5 * st->history[i - win]) {
                 status = ORC_E_STAGNATED;
                 break;
             }

@@ -37,6 +37,45 @@ struct Variant {
     int sigma;        // 0: sigma = 1, 1: coefficient array
 };
 
+// One operation of a coarse-level run executed by k_coarse.
+enum { kOpFill = 0, kOpSweep = 1, kOpProlong = 2, kOpInject = 3, kOpRestrict = 4 };
+struct CoarseOp {
+    int kind;         // kOp*
+    int m;            // nodes per axis of the level written
+    int level;        // sweeps: index into the level table
+    int first;        // prolongation: the finer level's stale values are zero
+    int target;       // sweeps: reduction target of the pseudo-residual, -1 for none
+    int pad;
+    const void *in0;  // sweep: e in; prolong: coarse e; inject / restrict: finer level
+    const void *in1;  // sweep: source g; prolong: stale finer e
+    const void *in2;  // sweep: coefficient (or null)
+    void *out;
+};
+// threads of the coarse-level workgroup: 16 waves in 2D; 8 in 3D, where the
+// 27-point stencil needs more than the 128 registers a 16-wave group allows
+constexpr int coarse_threads(int dim) { return dim == 3 ? 512 : 1024; }
+
+// A fused visit of a 2D level: optional interpolation of the next coarser
+// level's pending variation (prologue), `sweeps` relaxations, optional
+// injection of the result into the next coarser level (epilogue).
+constexpr int kMaxFusedSweeps = 6;
+struct VisitArgs {
+    const void *estale;   // level values before the visit (stale finer copy when interpolating)
+    const void *ecoarse;  // interpolation: values of the next coarser level
+    const void *g;        // source of the level
+    const void *sig;      // coefficient of the level (or null)
+    const double *G;      // Dirichlet values (full grid) or null
+    void *eout;           // values after the visit
+    void *einj;           // injection target (next coarser level) or null
+    unsigned long long *targets;
+    Level L;
+    int first;            // interpolation: the stale values are zero
+    int sweeps;           // 1 .. kMaxFusedSweeps
+    int prolong, inject;  // prologue / epilogue present
+    int pres[kMaxFusedSweeps];  // reduction target per relaxation, -1 for none
+};
+bool fused_visit_supported(int sweeps);
+
 // Precision-generic launchers (T = double or float); all enqueue on `st`.
 template <typename T>
 void launch_fill(T *p, size_t count, T value, hipStream_t st);
@@ -44,6 +83,13 @@ void launch_fill(T *p, size_t count, T value, hipStream_t st);
 template <typename T>
 void launch_sweep(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
                   const double *G, unsigned long long *pres, hipStream_t st);
+
+template <typename T>
+void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level *levels, const double *G,
+                   unsigned long long *targets, hipStream_t st);
+
+template <typename T>
+void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
 
 template <typename T>
 void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first,

@@ -18,7 +18,7 @@
 // is linear and nested (interpolating level nu to level nu-1 and then on
 // reproduces the direct interpolation), this gives the values the full-grid
 // formulation gives, up to rounding order.
-#include "sgml_internal.h"
+#include "sgml_device.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -30,36 +30,6 @@ namespace {
 
 constexpr int BX = 64;  // one wavefront along x
 constexpr int BY = 4;
-
-__device__ __forceinline__ size_t lin(int i, int j, int k, int m)
-{
-    return ((size_t)k * (size_t)m + (size_t)j) * (size_t)m + (size_t)i;
-}
-
-// Image of a coordinate across a face (node reflection).  For unknown nodes
-// it only triggers at Neumann faces: an unknown is never on a Dirichlet face.
-__device__ __forceinline__ int mir(int c, int m)
-{
-    c = c < 0 ? -c : c;
-    return c > m - 1 ? 2 * (m - 1) - c : c;
-}
-
-template <int DIM>
-__device__ __forceinline__ bool is_dir(int i, int j, int k, int m, unsigned dir)
-{
-    bool d = ((dir & 1u) && i == 0) || ((dir & 2u) && i == m - 1) || ((dir & 4u) && j == 0) ||
-             ((dir & 8u) && j == m - 1);
-    if (DIM == 3) d = d || ((dir & 16u) && k == 0) || ((dir & 32u) && k == m - 1);
-    return d;
-}
-
-// Order-independent max of non-negative doubles (and NaN, whose bit pattern
-// with a clear sign bit exceeds that of +inf): integer max of the bits,
-// accumulated per block and then into one slot of a reduction target.
-__device__ __forceinline__ unsigned long long dbits(double x)
-{
-    return (unsigned long long)__double_as_longlong(fabs(x));
-}
 
 __device__ __forceinline__ void block_max(unsigned long long v, unsigned long long *out)
 {
@@ -194,45 +164,38 @@ __global__ void k_fill(T *p, size_t count, T value)
 }
 
 // One relaxation (forward-Euler step of eq. (2), Algorithm 2 lines 3-4) of
-// all nodes of a level, Jacobi style: reads ein, writes eout.  Unknowns:
+// one node of a level, Jacobi style: reads ein, writes eout.  Unknowns:
 // e += theta/D (dL e - g).  Dirichlet nodes take the prescribed value G (the
-// variation G - e of Sec. 2) or 0.  pres (optional): max |dL e - g|.
+// variation G - e of Sec. 2) or 0.  Returns the bits of |dL e - g|.
 template <typename T, int DIM, int RAD, int SIG>
-__global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ ein, T *__restrict__ eout,
-                                               const T *__restrict__ g, const T *__restrict__ sig,
-                                               const double *__restrict__ G, Level L,
-                                               unsigned long long *__restrict__ pres)
+__device__ __forceinline__ unsigned long long sweep_node(const T *__restrict__ ein, T *__restrict__ eout,
+                                                         const T *__restrict__ g, const T *__restrict__ sig,
+                                                         const double *__restrict__ G, const Level &L,
+                                                         int i, int j, int k)
 {
-    int i, j, k;
-    unsigned long long rb = 0;
-    if (node_of<DIM>(L.m, i, j, k)) {
-        const size_t c = lin(i, j, k, L.m);
-        if (is_dir<DIM>(i, j, k, L.m, L.dir)) {
-            eout[c] = G ? (T)G[lin(i * L.lam, j * L.lam, k * L.lam, L.N)] : T(0);
-        } else {
-            T Lu, D;
-            stencil<T, DIM, RAD, SIG>(ein, sig, i, j, k, L.m, (T)L.scale, (T)L.a, Lu, D);
-            const T r = Lu - g[c];
-            eout[c] = ein[c] + ((T)L.theta / D) * r;
-            rb = dbits((double)r);
-        }
+    const size_t c = lin(i, j, k, L.m);
+    if (is_dir<DIM>(i, j, k, L.m, L.dir)) {
+        eout[c] = G ? (T)G[lin(i * L.lam, j * L.lam, k * L.lam, L.N)] : T(0);
+        return 0;
     }
-    if (pres) block_max(rb, pres);
+    T Lu, D;
+    stencil<T, DIM, RAD, SIG>(ein, sig, i, j, k, L.m, (T)L.scale, (T)L.a, Lu, D);
+    const T r = Lu - g[c];
+    eout[c] = ein[c] + ((T)L.theta / D) * r;
+    return dbits((double)r);
 }
 
 // Interpolation of the pending variation of level nu (compact, mc nodes per
-// axis) to level nu-1 (mf = 2 mc - 1): the pending variation at a coarse node
-// X is ec(X) - ef_in(2X) (zero stale values on the level's first visit of a
-// cycle); coarse nodes take ec directly, the others add the multilinear
-// (tensor hat) interpolation -- the mean of the 2, 4 or 8 enclosing coarse
-// nodes.
+// axis) to node (i,j,k) of level nu-1 (mf = 2 mc - 1): the pending variation
+// at a coarse node X is ec(X) - ef_in(2X) (zero stale values on the level's
+// first visit of a cycle); coarse nodes take ec directly, the others add the
+// multilinear (tensor hat) interpolation -- the mean of the 2, 4 or 8
+// enclosing coarse nodes.
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_prolong(const T *__restrict__ ec, const T *__restrict__ efin,
-                                                 T *__restrict__ efout, int mc, int first)
+__device__ __forceinline__ void prolong_node(const T *__restrict__ ec, const T *__restrict__ efin,
+                                             T *__restrict__ efout, int mc, int first, int i, int j, int k)
 {
     const int mf = 2 * mc - 1;
-    int i, j, k;
-    if (!node_of<DIM>(mf, i, j, k)) return;
     const int ci = i >> 1, cj = j >> 1, ck = k >> 1;
     const int oi = i & 1, oj = j & 1, ok = DIM == 3 ? (k & 1) : 0;
     const size_t f = lin(i, j, k, mf);
@@ -262,13 +225,11 @@ __global__ __launch_bounds__(256) void k_prolong(const T *__restrict__ ec, const
 }
 
 // Values of level nu-1 at the level-nu nodes (the schedule climbs a level).
-template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_inject(const T *__restrict__ ef, T *__restrict__ ec, int mc)
+template <typename T>
+__device__ __forceinline__ void inject_node(const T *__restrict__ ef, T *__restrict__ ec, int mc, int i, int j,
+                                            int k)
 {
-    const int mf = 2 * mc - 1;
-    int i, j, k;
-    if (!node_of<DIM>(mc, i, j, k)) return;
-    ec[lin(i, j, k, mc)] = ef[lin(2 * i, 2 * j, 2 * k, mf)];
+    ec[lin(i, j, k, mc)] = ef[lin(2 * i, 2 * j, 2 * k, 2 * mc - 1)];
 }
 
 // One restriction step, eq. (3) / eq. (4): the coarse node X averages the
@@ -276,13 +237,11 @@ __global__ __launch_bounds__(256) void k_inject(const T *__restrict__ ef, T *__r
 // samples outside the grid are images.  Summed in the same order (z, y, x
 // outer to inner) with exactly representable weights.
 template <typename Tin, typename Tout, int DIM>
-__global__ __launch_bounds__(256) void k_restrict(const Tin *__restrict__ fine, Tout *__restrict__ coarse,
-                                                  int mc)
+__device__ __forceinline__ void restrict_node(const Tin *__restrict__ fine, Tout *__restrict__ coarse, int mc,
+                                              int i, int j, int k)
 {
     using Acc = typename std::conditional<sizeof(Tin) == 8 || sizeof(Tout) == 8, double, float>::type;
     const int mf = 2 * mc - 1;
-    int i, j, k;
-    if (!node_of<DIM>(mc, i, j, k)) return;
     Acc acc = Acc(0);
 #pragma unroll
     for (int r = (DIM == 3 ? -1 : 0); r <= (DIM == 3 ? 1 : 0); ++r) {
@@ -300,6 +259,91 @@ __global__ __launch_bounds__(256) void k_restrict(const Tin *__restrict__ fine, 
         }
     }
     coarse[lin(i, j, k, mc)] = (Tout)(acc / Acc(1 << DIM));
+}
+
+template <typename T, int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ ein, T *__restrict__ eout,
+                                               const T *__restrict__ g, const T *__restrict__ sig,
+                                               const double *__restrict__ G, Level L,
+                                               unsigned long long *__restrict__ pres)
+{
+    int i, j, k;
+    unsigned long long rb = 0;
+    if (node_of<DIM>(L.m, i, j, k)) rb = sweep_node<T, DIM, RAD, SIG>(ein, eout, g, sig, G, L, i, j, k);
+    if (pres) block_max(rb, pres);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_prolong(const T *__restrict__ ec, const T *__restrict__ efin,
+                                                 T *__restrict__ efout, int mc, int first)
+{
+    int i, j, k;
+    if (node_of<DIM>(2 * mc - 1, i, j, k)) prolong_node<T, DIM>(ec, efin, efout, mc, first, i, j, k);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_inject(const T *__restrict__ ef, T *__restrict__ ec, int mc)
+{
+    int i, j, k;
+    if (node_of<DIM>(mc, i, j, k)) inject_node<T>(ef, ec, mc, i, j, k);
+}
+
+template <typename Tin, typename Tout, int DIM>
+__global__ __launch_bounds__(256) void k_restrict(const Tin *__restrict__ fine, Tout *__restrict__ coarse,
+                                                  int mc)
+{
+    int i, j, k;
+    if (node_of<DIM>(mc, i, j, k)) restrict_node<Tin, Tout, DIM>(fine, coarse, mc, i, j, k);
+}
+
+// The coarse levels of a cycle in one launch of one workgroup: a run of
+// consecutive operations (restriction, zero fill, relaxation, interpolation,
+// injection) on levels small enough to live in L2, executed in order with a
+// workgroup barrier between operations.  Waves stride over rows, lanes over
+// the nodes of a row.
+template <typename T, int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse(const CoarseOp *__restrict__ ops, int nops,
+                                                           const Level *__restrict__ levels,
+                                                           const double *__restrict__ G,
+                                                           unsigned long long *__restrict__ targets)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int waves = coarse_threads(DIM) / 64;
+    for (int o = 0; o < nops; ++o) {
+        const CoarseOp op = ops[o];
+        const int m = op.m;
+        const int rows = DIM == 3 ? m * m : m;
+        unsigned long long rb = 0;
+        for (int r = wave; r < rows; r += waves) {
+            const int j = DIM == 3 ? r % m : r, k = DIM == 3 ? r / m : 0;
+            for (int i = lane; i < m; i += 64) {
+                switch (op.kind) {
+                case kOpFill:
+                    ((T *)op.out)[lin(i, j, k, m)] = T(0);
+                    break;
+                case kOpSweep: {
+                    const unsigned long long b = sweep_node<T, DIM, RAD, SIG>(
+                        (const T *)op.in0, (T *)op.out, (const T *)op.in1, (const T *)op.in2, G,
+                        levels[op.level], i, j, k);
+                    rb = b > rb ? b : rb;
+                    break;
+                }
+                case kOpProlong:
+                    prolong_node<T, DIM>((const T *)op.in0, (const T *)op.in1, (T *)op.out, (m + 1) / 2,
+                                         op.first, i, j, k);
+                    break;
+                case kOpInject:
+                    inject_node<T>((const T *)op.in0, (T *)op.out, m, i, j, k);
+                    break;
+                default:  // kOpRestrict
+                    restrict_node<T, T, DIM>((const T *)op.in0, (T *)op.out, m, i, j, k);
+                    break;
+                }
+            }
+        }
+        if (op.kind == kOpSweep && op.target >= 0) block_max(rb, targets + (size_t)op.target * kRedWords);
+        __syncthreads();
+    }
 }
 
 template <typename Tin, typename Tout>
@@ -513,6 +557,28 @@ void launch_sweep(const Variant &v, const Level &L, const T *ein, T *eout, const
     dispatch3<SweepRun<T>::template K>(v, L, ein, eout, g, sig, G, pres, st);
 }
 
+namespace {
+template <typename T>
+struct CoarseRun {
+    template <int D, int R, int S>
+    struct K {
+        static void run(const CoarseOp *ops, int nops, const Level *levels, const double *G,
+                        unsigned long long *targets, hipStream_t st)
+        {
+            hipLaunchKernelGGL((k_coarse<T, D, R, S>), dim3(1), dim3(coarse_threads(D)), 0, st, ops, nops,
+                               levels, G, targets);
+        }
+    };
+};
+}  // namespace
+
+template <typename T>
+void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level *levels, const double *G,
+                   unsigned long long *targets, hipStream_t st)
+{
+    dispatch3<CoarseRun<T>::template K>(v, ops, nops, levels, G, targets, st);
+}
+
 template <typename T>
 void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)
 {
@@ -645,6 +711,10 @@ template void launch_sweep<double>(const Variant &, const Level &, const double 
                                    const double *, const double *, unsigned long long *, hipStream_t);
 template void launch_sweep<float>(const Variant &, const Level &, const float *, float *, const float *,
                                   const float *, const double *, unsigned long long *, hipStream_t);
+template void launch_coarse<double>(const Variant &, const CoarseOp *, int, const Level *, const double *,
+                                    unsigned long long *, hipStream_t);
+template void launch_coarse<float>(const Variant &, const CoarseOp *, int, const Level *, const double *,
+                                   unsigned long long *, hipStream_t);
 template void launch_prolong<double>(int, int, const double *, const double *, double *, bool, hipStream_t);
 template void launch_prolong<float>(int, int, const float *, const float *, float *, bool, hipStream_t);
 template void launch_inject<double>(int, int, const double *, double *, hipStream_t);

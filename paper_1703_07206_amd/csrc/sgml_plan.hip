@@ -23,8 +23,11 @@ constexpr size_t kScalars = (size_t)kTargets * kRedWords;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+constexpr int kMaxCoarseOps = 4096;
+constexpr int kDefaultCoarseNodes = 5000;
+
 struct Layout {
-    size_t scal, s, e0, shat, sig0t;
+    size_t scal, ops, levels, s, e0, shat, sig0t;
     size_t e[kMaxLevels][2], g[kMaxLevels], sig64[kMaxLevels], sigt[kMaxLevels];
     size_t total;
 };
@@ -64,6 +67,8 @@ Layout make_layout(const sgml_problem *p, int precision)
         return o;
     };
     L.scal = take(sizeof(unsigned long long) * kScalars);
+    L.ops = take(sizeof(CoarseOp) * kMaxCoarseOps);
+    L.levels = take(sizeof(Level) * kMaxLevels);
     L.s = take(8 * M);
     L.e0 = take(2 * 8 * M);  // two level-0 buffers, FP64-sized (FP32 uses half)
     L.shat = mixed ? take(4 * M) : 0;
@@ -133,6 +138,8 @@ struct sgml_plan {
     hipEvent_t ev0, ev1;
     std::vector<hipEvent_t> pev;  // profiling events, pairs around timed launches
     size_t pev_used = 0;
+    CoarseOp *ops_host;           // pinned staging of the coarse operation list
+    Level *levels_host;           // pinned staging of the level table
 
     template <typename T>
     T *at(size_t off) const
@@ -216,14 +223,31 @@ double as_double(unsigned long long b)
     return d;
 }
 
-// One cycle of Algorithm 3 from e = 0 on the level-0 source src0, in T.
-// Returns the level-0 buffer holding the cycle's e.
+// A launch timed with a pair of events (profiling).
+struct Timed {
+    int cls, sweeps;
+    hipEvent_t *ev;
+};
+
+// A cycle compiled to a list of operations (the same list every cycle).
+constexpr int kOpVisit = 5;  // fused visit of a 2D level (host-side operation)
+
+struct HostOp {
+    CoarseOp op;
+    bool coarse;     // runs inside the one-workgroup coarse kernel
+    VisitArgs visit;  // kOpVisit
+};
+
+// Compile one cycle of Algorithm 3 from e = 0 on the level-0 source src0, in
+// T: the restriction pyramid of the source (Algorithm 1), then every visit
+// with the level transitions it needs.  Returns the level-0 buffer that holds
+// the cycle's e at the end.
 template <typename T>
-const T *run_cycle(sgml_plan *P, const T *src0, const double *G, const std::vector<int> &lev,
-                   const std::vector<int> &cnt, bool record, bool profile,
-                   std::vector<std::pair<int, hipEvent_t *>> &timed, long long &updates, hipStream_t st)
+const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev, const std::vector<int> &cnt,
+                       bool record, int coarse_level, bool fuse, std::vector<HostOp> &ops,
+                       long long &updates_per_cycle)
 {
-    const int n = P->n, dim = P->dim;
+    const int n = P->n;
     const bool mixed = sizeof(T) == 4;
     T *E[kMaxLevels][2];
     const T *g[kMaxLevels];
@@ -232,6 +256,26 @@ const T *run_cycle(sgml_plan *P, const T *src0, const double *G, const std::vect
     E[0][1] = E[0][0] + P->M;
     g[0] = src0;
     sig[0] = P->var.sigma ? (mixed ? (const T *)P->at<T>(P->lay.sig0t) : (const T *)P->sigma) : nullptr;
+    ops.clear();
+    updates_per_cycle = 0;
+    auto push = [&](int kind, int level, int first, int target, const void *in0, const void *in1,
+                    const void *in2, void *out, bool coarse) {
+        HostOp h;
+        std::memset(&h, 0, sizeof(h));
+        h.op.kind = kind;
+        h.op.m = P->m(level);
+        h.op.level = level;
+        h.op.first = first;
+        h.op.target = target;
+        h.op.in0 = in0;
+        h.op.in1 = in1;
+        h.op.in2 = in2;
+        h.op.out = out;
+        h.coarse = coarse;
+        ops.push_back(h);
+    };
+    // visits of large 2D levels run as fused passes
+    auto fusable = [&](int nu) { return fuse && P->dim == 2 && nu < coarse_level && P->m(nu) >= 64; };
     for (int nu = 1; nu < n; ++nu) {
         E[nu][0] = P->at<T>(P->lay.e[nu][0]);
         E[nu][1] = P->at<T>(P->lay.e[nu][1]);
@@ -241,49 +285,208 @@ const T *run_cycle(sgml_plan *P, const T *src0, const double *G, const std::vect
                                         : (const T *)P->at<T>(P->lay.sig64[nu]))
                                : nullptr;
         // restriction(nu) of the cycle source (Algorithm 1), kept for the cycle
-        launch_restrict<T, T>(dim, P->m(nu), g[nu - 1], gn, st);
+        push(kOpRestrict, nu, 0, -1, g[nu - 1], nullptr, nullptr, gn, nu - 1 >= coarse_level);
     }
     int cur[kMaxLevels] = {0};
     bool seen[kMaxLevels] = {false};
     int prev = -1;
     for (size_t v = 0; v < lev.size(); ++v) {
         const int nu = lev[v];
-        if (prev < 0) {
-            launch_fill<T>(E[nu][cur[nu]], level_nodes(dim, n, nu), T(0), st);
-        }
+        if (prev < 0) push(kOpFill, nu, 0, -1, nullptr, nullptr, nullptr, E[nu][cur[nu]], nu >= coarse_level);
         // walk one level at a time: refining interpolates the pending
         // variation into the finer level, coarsening copies the finer values
         while (prev > nu) {
             const int f = prev - 1;
-            launch_prolong<T>(dim, P->m(prev), E[prev][cur[prev]], E[f][cur[f]], E[f][cur[f] ^ 1],
-                              !seen[f], st);
+            push(kOpProlong, f, !seen[f], -1, E[prev][cur[prev]], E[f][cur[f]], nullptr, E[f][cur[f] ^ 1],
+                 f >= coarse_level);
             cur[f] ^= 1;
             seen[f] = true;
             prev = f;
         }
         while (prev >= 0 && prev < nu) {
             const int c = prev + 1;
-            launch_inject<T>(dim, P->m(c), E[prev][cur[prev]], E[c][cur[c]], st);
+            HostOp *last = ops.empty() ? nullptr : &ops.back();
+            if (last && last->op.kind == kOpVisit && last->op.level == prev && !last->visit.inject) {
+                // injection as the epilogue of the fused visit; it writes the
+                // other buffer of level c, whose current one the visit reads
+                last->visit.inject = 1;
+                last->visit.einj = E[c][cur[c] ^ 1];
+                cur[c] ^= 1;
+            } else {
+                push(kOpInject, c, 0, -1, E[prev][cur[prev]], nullptr, nullptr, E[c][cur[c]],
+                     prev >= coarse_level);
+            }
             seen[c] = true;
             prev = c;
         }
         seen[nu] = true;
-        const Level L = P->level(nu);
-        for (int r = 0; r < cnt[v]; ++r) {
-            unsigned long long *pr = (record && r == cnt[v] - 1) ? target(P, kPres + (int)v) : nullptr;
-            hipEvent_t *ev = (profile && nu == 0) ? prof_pair(P) : nullptr;
-            if (ev) (void)hipEventRecord(ev[0], st);
-            launch_sweep<T>(P->var, L, E[nu][cur[nu]], E[nu][cur[nu] ^ 1], g[nu], sig[nu], G, pr, st);
-            if (ev) {
-                (void)hipEventRecord(ev[1], st);
-                timed.emplace_back(0, ev);
+        updates_per_cycle += (long long)cnt[v] * (long long)level_nodes(P->dim, n, nu);
+        const int tgt_last = record ? kPres + (int)v : -1;
+        if (!fusable(nu)) {
+            for (int r = 0; r < cnt[v]; ++r) {
+                push(kOpSweep, nu, 0, r == cnt[v] - 1 ? tgt_last : -1, E[nu][cur[nu]], g[nu], sig[nu],
+                     E[nu][cur[nu] ^ 1], nu >= coarse_level);
+                cur[nu] ^= 1;
             }
-            cur[nu] ^= 1;
+            prev = nu;
+            continue;
         }
-        updates += (long long)cnt[v] * (long long)level_nodes(dim, n, nu);
+        int left = cnt[v];
+        // continue the previous fused visit of this level when nothing came between
+        HostOp *last = ops.empty() ? nullptr : &ops.back();
+        if (last && last->op.kind == kOpVisit && last->op.level == nu && !last->visit.inject &&
+            fused_visit_supported(last->visit.sweeps + left)) {
+            last->visit.pres[last->visit.sweeps + left - 1] = tgt_last;
+            last->visit.sweeps += left;
+            prev = nu;
+            continue;
+        }
+        // a preceding interpolation into this level becomes the prologue
+        bool pro = false;
+        const void *ecoarse = nullptr, *estale = E[nu][cur[nu]];
+        int first = 0;
+        void *out0 = nullptr;
+        if (last && last->op.kind == kOpProlong && last->op.level == nu) {
+            pro = true;
+            ecoarse = last->op.in0;
+            estale = last->op.in1;
+            first = last->op.first;
+            out0 = last->op.out;  // cur[nu] already points at it
+            ops.pop_back();
+        }
+        while (left > 0) {
+            int s = kMaxFusedSweeps;
+            while (s > left || !fused_visit_supported(s)) --s;
+            HostOp h;
+            std::memset(&h, 0, sizeof(h));
+            h.op.kind = kOpVisit;
+            h.op.level = nu;
+            h.op.m = P->m(nu);
+            VisitArgs &a = h.visit;
+            a.estale = estale;
+            a.ecoarse = ecoarse;
+            a.g = g[nu];
+            a.sig = sig[nu];
+            a.first = first;
+            a.sweeps = s;
+            a.prolong = pro;
+            a.inject = 0;
+            for (int k = 0; k < kMaxFusedSweeps; ++k) a.pres[k] = -1;
+            if (pro) {
+                a.eout = out0;
+            } else {
+                a.eout = E[nu][cur[nu] ^ 1];
+                cur[nu] ^= 1;
+            }
+            left -= s;
+            if (left == 0) a.pres[s - 1] = tgt_last;
+            ops.push_back(h);
+            estale = a.eout;
+            pro = false;
+            first = 0;
+        }
         prev = nu;
     }
     return E[0][cur[0]];
+}
+
+// Upload the coarse operations (in execution order) and the level table; the
+// device copy serves every cycle of the solve.  Coarse runs beyond the
+// buffer's capacity fall back to separate launches.
+sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, hipStream_t st)
+{
+    int nc = 0;
+    for (auto &h : ops) {
+        if (!h.coarse) continue;
+        if (nc >= kMaxCoarseOps) {
+            h.coarse = false;
+            continue;
+        }
+        P->ops_host[nc++] = h.op;
+    }
+    for (int nu = 0; nu < P->n; ++nu) P->levels_host[nu] = P->level(nu);
+    if (nc) SGML_HIP(hipMemcpyAsync(P->at<CoarseOp>(P->lay.ops), P->ops_host, sizeof(CoarseOp) * nc,
+                                    hipMemcpyHostToDevice, st));
+    SGML_HIP(hipMemcpyAsync(P->at<Level>(P->lay.levels), P->levels_host, sizeof(Level) * P->n,
+                            hipMemcpyHostToDevice, st));
+    return SGML_OK;
+}
+
+// Enqueue one cycle: runs of coarse operations as one k_coarse launch each,
+// the rest as grid launches; level-0 relaxations timed when profiling.
+template <typename T>
+sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *G, bool profile,
+                    std::vector<Timed> &timed, hipStream_t st)
+{
+    const CoarseOp *dev_ops = P->at<CoarseOp>(P->lay.ops);
+    const Level *dev_levels = P->at<Level>(P->lay.levels);
+    unsigned long long *targets = target(P, 0);
+    int coarse_done = 0;
+    for (size_t i = 0; i < ops.size();) {
+        if (ops[i].coarse) {
+            size_t j = i;
+            while (j < ops.size() && ops[j].coarse) ++j;
+            const int cnt = (int)(j - i);
+            launch_coarse<T>(P->var, dev_ops + coarse_done, cnt, dev_levels, G, targets, st);
+            coarse_done += cnt;
+            i = j;
+            continue;
+        }
+        const CoarseOp &o = ops[i].op;
+        if (o.kind == kOpVisit) {
+            VisitArgs a = ops[i].visit;
+            a.G = G;
+            a.targets = targets;
+            a.L = P->level(o.level);
+            const int cls = a.inject ? SGML_PROF_VISIT0_INJ : SGML_PROF_VISIT0;
+            hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
+            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            launch_visit2d<T>(P->var, a, st);
+            if (ev) {
+                SGML_HIP(hipEventRecord(ev[1], st));
+                timed.push_back({cls, a.sweeps, ev});
+            }
+            ++i;
+            continue;
+        }
+        switch (o.kind) {
+        case kOpFill:
+            launch_fill<T>((T *)o.out, level_nodes(P->dim, P->n, o.level), T(0), st);
+            break;
+        case kOpRestrict:
+            launch_restrict<T, T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
+            break;
+        case kOpProlong:
+            launch_prolong<T>(P->dim, (o.m + 1) / 2, (const T *)o.in0, (const T *)o.in1, (T *)o.out,
+                              o.first != 0, st);
+            break;
+        case kOpInject:
+            launch_inject<T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
+            break;
+        default: {
+            hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
+            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            launch_sweep<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1,
+                            (const T *)o.in2, G, o.target >= 0 ? target(P, o.target) : nullptr, st);
+            if (ev) {
+                SGML_HIP(hipEventRecord(ev[1], st));
+                timed.push_back({SGML_PROF_SWEEP0, 1, ev});
+            }
+            break;
+        }
+        }
+        ++i;
+    }
+    return SGML_OK;
+}
+
+int coarse_level_of(const sgml_plan *P, int coarse_nodes)
+{
+    if (coarse_nodes < 0) return kMaxLevels;  // disabled
+    const size_t limit = coarse_nodes == 0 ? kDefaultCoarseNodes : (size_t)coarse_nodes;
+    int nu = P->n;
+    while (nu > 0 && level_nodes(P->dim, P->n, nu - 1) <= limit) --nu;
+    return nu;
 }
 
 template <typename T>
@@ -318,6 +521,13 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
         launch_set_dirichlet(L0, P->dim, G, u, st);
         status = std::isfinite(norm0) ? SGML_OK : SGML_E_ARG;
     } else {
+        std::vector<HostOp> ops;
+        long long updates_per_cycle = 0;
+        const T *e = compile_cycle<T>(P, src0, lev, cnt, o->record_pres != 0,
+                                      coarse_level_of(P, o->coarse_nodes), o->fuse >= 0, ops,
+                                      updates_per_cycle);
+        rc = upload_ops(P, ops, st);
+        if (rc != SGML_OK) return rc;
         int k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
         if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
         double last = norm0;
@@ -325,10 +535,11 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             const double *Gc = i == 0 ? G : nullptr;
             clear_targets(P, 0, 1, st);
             if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
-            std::vector<std::pair<int, hipEvent_t *>> timed;
+            std::vector<Timed> timed;
             P->pev_used = 0;
-            const T *e = run_cycle<T>(P, src0, Gc, lev, cnt, o->record_pres != 0, o->profile != 0, timed,
-                                      S.node_updates, st);
+            rc = run_ops<T>(P, ops, Gc, o->profile != 0, timed, st);
+            if (rc != SGML_OK) return rc;
+            S.node_updates += updates_per_cycle;
             // next cycle's scaling from the last known residual norm (lagged)
             const int k_next = mixed ? std::ilogb(last) : 0;
             hipEvent_t *ev = o->profile ? prof_pair(P) : nullptr;
@@ -337,21 +548,17 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                                std::ldexp(1.0, -k_next), target(P, 0), st);
             if (ev) {
                 SGML_HIP(hipEventRecord(ev[1], st));
-                timed.emplace_back(1, ev);
+                timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
             }
             SGML_HIP(hipGetLastError());
             rc = fetch(P, 0, 1, st);
             if (rc != SGML_OK) return rc;
             for (auto &t : timed) {
                 float ms = 0.f;
-                SGML_HIP(hipEventElapsedTime(&ms, t.second[0], t.second[1]));
-                if (t.first == 0) {
-                    S.sweep0_ms += ms;
-                    S.sweep0_launches++;
-                } else {
-                    S.boundary_ms += ms;
-                    S.boundary_launches++;
-                }
+                SGML_HIP(hipEventElapsedTime(&ms, t.ev[0], t.ev[1]));
+                S.prof_ms[t.cls] += ms;
+                S.prof_launches[t.cls]++;
+                S.prof_sweeps[t.cls] += t.sweeps;
             }
             const double norm = host_max(P, 0);
             const double rel = norm / norm0;
@@ -368,7 +575,8 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                 status = SGML_OK;
                 break;
             }
-            if (i >= 3 && i - 3 < SGML_HIST && rel > 0.5 * S.history[i - 3]) {
+            const int win = o->stall_window == 0 ? 3 : o->stall_window;
+            if (win > 0 && i >= win && i < SGML_HIST && rel > 0.5 * S.history[i - win]) {
                 status = SGML_E_STAGNATED;
                 break;
             }
@@ -442,7 +650,14 @@ sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *work
         delete P;
         return SGML_E_HIP;
     }
-    if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) {
+    P->ops_host = nullptr;
+    P->levels_host = nullptr;
+    if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess ||
+        hipHostMalloc((void **)&P->ops_host, sizeof(CoarseOp) * kMaxCoarseOps, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&P->levels_host, sizeof(Level) * kMaxLevels, hipHostMallocDefault) !=
+            hipSuccess) {
+        if (P->ops_host) (void)hipHostFree(P->ops_host);
         (void)hipHostFree(P->host);
         delete P;
         return SGML_E_HIP;
@@ -565,6 +780,8 @@ void sgml_plan_destroy(sgml_plan *P)
     (void)hipEventDestroy(P->ev0);
     (void)hipEventDestroy(P->ev1);
     for (hipEvent_t e : P->pev) (void)hipEventDestroy(e);
+    (void)hipHostFree(P->ops_host);
+    (void)hipHostFree(P->levels_host);
     (void)hipHostFree(P->host);
     delete P;
 }

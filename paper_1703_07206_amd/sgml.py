@@ -21,6 +21,8 @@ FP64, MIXED = 0, 1
 SCHEDULE_ONCE, SCHEDULE_EACH = 0, 1
 HIST = 512
 MAX_VISITS = 128
+PROF_CLASSES = 4
+PROF_NAMES = ("sweep0", "visit0_inject", "visit0", "cycle_end")
 
 
 class Problem(ctypes.Structure):
@@ -31,7 +33,9 @@ class Problem(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_cycles", ctypes.c_int), ("n_r", ctypes.c_int),
                 ("schedule", ctypes.c_int), ("precision", ctypes.c_int),
-                ("record_pres", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("record_pres", ctypes.c_int), ("profile", ctypes.c_int),
+                ("coarse_nodes", ctypes.c_int), ("stall_window", ctypes.c_int),
+                ("fuse", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -39,15 +43,18 @@ class Stats(ctypes.Structure):
                 ("relres", ctypes.c_double), ("history", ctypes.c_double * HIST),
                 ("visits", ctypes.c_int), ("pres", ctypes.c_double * MAX_VISITS),
                 ("node_updates", ctypes.c_longlong), ("ms", ctypes.c_float),
-                ("sweep0_launches", ctypes.c_int), ("sweep0_ms", ctypes.c_float),
-                ("boundary_launches", ctypes.c_int), ("boundary_ms", ctypes.c_float)]
+                ("prof_launches", ctypes.c_int * PROF_CLASSES),
+                ("prof_ms", ctypes.c_float * PROF_CLASSES),
+                ("prof_sweeps", ctypes.c_int * PROF_CLASSES)]
 
     def as_dict(self):
         return dict(status=self.status, cycles=self.cycles, norm0=self.norm0, relres=self.relres,
                     history=list(self.history[:min(self.cycles, HIST)]),
                     pres=list(self.pres[:self.visits]), node_updates=self.node_updates,
-                    ms=self.ms, sweep0_launches=self.sweep0_launches, sweep0_ms=self.sweep0_ms,
-                    boundary_launches=self.boundary_launches, boundary_ms=self.boundary_ms)
+                    ms=self.ms,
+                    prof={PROF_NAMES[c]: dict(launches=self.prof_launches[c], ms=self.prof_ms[c],
+                                              sweeps=self.prof_sweeps[c])
+                          for c in range(PROF_CLASSES)})
 
 
 class SGMLError(RuntimeError):
@@ -182,9 +189,9 @@ class Plan:
             raise SGMLError(rc, "sgml_plan_set_coeffs")
 
     def opts(self, tol=1e-12, max_cycles=100, n_r=2, schedule=SCHEDULE_ONCE, precision=None,
-             record_pres=False, profile=False):
+             record_pres=False, profile=False, coarse_nodes=0, stall_window=0, fuse=0):
         return Opts(tol, max_cycles, n_r, schedule, self.precision if precision is None else precision,
-                    int(record_pres), int(profile))
+                    int(record_pres), int(profile), int(coarse_nodes), int(stall_window), int(fuse))
 
     def solve(self, f, G=None, u=None, raise_on_failure=True, stream=None, **kw):
         """Solve dL(u) = f; returns (u, stats dict)."""

@@ -205,3 +205,65 @@ def test_solves_are_deterministic():
     m1, _ = gpu_solve(wl, "mixed", tol=1e-13)
     m2, _ = gpu_solve(wl, "mixed", tol=1e-13)
     assert np.array_equal(m1, m2)
+
+
+@pytest.mark.parametrize("coarse_nodes", [-1, 0, 10 ** 6], ids=["separate", "default", "all-coarse"])
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[7], CASES[9], CASES[10]],
+                         ids=[IDS[2], IDS[3], IDS[7], IDS[9], IDS[10]])
+def test_coarse_level_kernel_paths(case, coarse_nodes):
+    # the same cycle with coarse levels launched one operation at a time, in
+    # one workgroup per run of coarse operations, or with every level there
+    dim, n, stencil, faces, hetero, a, with_G = case
+    wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1100 + n)
+    P = oracle_problem(wl)
+    u_or, _ = P.solve(wl.f, G=wl.G, tol=0.0, max_cycles=2)
+    _, pres_or = P.cycle(wl.f, G=wl.G, with_pres=True)
+    for prec, bar in (("fp64", 1e-12), ("mixed", 1e-5)):
+        u_gpu, st = gpu_solve(wl, prec, tol=0.0, max_cycles=2, coarse_nodes=coarse_nodes)
+        assert rel_inf(u_gpu, u_or) < bar, (prec, rel_inf(u_gpu, u_or))
+    _, st = gpu_solve(wl, tol=0.0, max_cycles=1, record_pres=True, coarse_nodes=coarse_nodes)
+    assert np.max(np.abs(np.array(st["pres"]) - pres_or)) <= 1e-11 * np.max(pres_or)
+
+
+FUSED_CASES = [
+    (2, 9, AXIS, "DDNN", False, 0.0, True),
+    (2, 9, RADIAL, "DNND", True, -0.3, True),
+    (2, 8, AXIS, "NNDD", True, 0.0, False),
+    (2, 8, RADIAL, "NDDN", False, -0.1, True),
+]
+FUSED_IDS = [f"n{n}-{'rad' if s else 'axis'}-{fc}-{'sig' if h else 'one'}" for d, n, s, fc, h, a, g in FUSED_CASES]
+
+
+@pytest.mark.parametrize("n_r,sched", [(2, 0), (1, 0), (3, 0), (2, 1), (0, 0)],
+                         ids=["nr2", "nr1", "nr3", "nr2-each", "full-doubling"])
+@pytest.mark.parametrize("case", FUSED_CASES, ids=FUSED_IDS)
+def test_fused_visits_match_oracle(case, n_r, sched):
+    # one pass per visit on the large 2D levels (interpolation prologue,
+    # several relaxations, injection epilogue) against the oracle, and
+    # against the unfused launches
+    dim, n, stencil, faces, hetero, a, with_G = case
+    if n_r == 0 and n > 8:
+        pytest.skip("full doubling at 513^2 is slow in the literal oracle")
+    wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1200 + n)
+    P = oracle_problem(wl)
+    u_or, info = P.solve(wl.f, G=wl.G, tol=0.0, max_cycles=2, n_r=n_r, reading=sched)
+    _, pres_or = P.cycle(wl.f, G=wl.G, n_r=n_r, reading=sched, with_pres=True)
+    for fuse in (0, -1):
+        u, st = gpu_solve(wl, tol=0.0, max_cycles=2, n_r=n_r, schedule=sched, fuse=fuse)
+        assert rel_inf(u, u_or) < 1e-12, (fuse, rel_inf(u, u_or))
+        um, _ = gpu_solve(wl, "mixed", tol=0.0, max_cycles=2, n_r=n_r, schedule=sched, fuse=fuse)
+        assert rel_inf(um, u_or) < 1e-5
+        _, st1 = gpu_solve(wl, tol=0.0, max_cycles=1, n_r=n_r, schedule=sched, fuse=fuse,
+                           record_pres=True)
+        assert np.max(np.abs(np.array(st1["pres"]) - pres_or)) <= 1e-11 * np.max(pres_or)
+
+
+@pytest.mark.parametrize("case", FUSED_CASES[:2], ids=FUSED_IDS[:2])
+def test_fused_visits_converged(case):
+    dim, n, stencil, faces, hetero, a, with_G = case
+    wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1300 + n)
+    u_or, _ = oracle_problem(wl).solve(wl.f, G=wl.G, tol=1e-15, max_cycles=200)
+    for prec, tol in (("fp64", 1e-15), ("mixed", 1e-14)):
+        u, st = gpu_solve(wl, prec, tol=tol, max_cycles=200)
+        assert st["status"] == 0
+        assert rel_inf(u, u_or) < 1e-12

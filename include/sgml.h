@@ -100,9 +100,11 @@ typedef struct {
                          0: default (5000), < 0: every operation launched alone */
     int stall_window; /* SGML_E_STAGNATED when the residual has not halved over
                          this many cycles; 0: default (3), < 0: never */
-    int fuse;         /* 2D levels too large for the coarse kernel: 0 (default)
-                         runs each visit as one fused pass, < 0 one launch per
-                         interpolation, relaxation and injection */
+    int fuse;         /* 2D levels with at least this many nodes per axis (and
+                         too large for the coarse kernel) run each visit as one
+                         fused pass; 0: default (1025), < 0: never (one launch per
+                         interpolation, relaxation and injection); values
+                         below 64 act as 64 */
 } sgml_opts;
 
 #define SGML_HIST 512

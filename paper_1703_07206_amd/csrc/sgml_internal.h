@@ -76,6 +76,19 @@ struct VisitArgs {
 };
 bool fused_visit_supported(int sweeps);
 
+// The cycle-end pass on a 2D level 0 (see k_boundary for the general form).
+struct CycleEndArgs {
+    const void *e;        // level-0 values of the cycle, in the cycle's precision
+    double escale;        // e = escale * E
+    const double *G;      // Dirichlet values (first cycle) or null
+    const double *sigma;  // coefficient (FP64, full grid) or null
+    double *u, *s;        // collected solution and recursive residual
+    void *shat;           // next cycle's source in the cycle's precision (mixed) or null
+    double shat_scale;
+    unsigned long long *norm;  // reduction target of max |s|
+    Level L;
+};
+
 // Precision-generic launchers (T = double or float); all enqueue on `st`.
 template <typename T>
 void launch_fill(T *p, size_t count, T value, hipStream_t st);
@@ -90,6 +103,9 @@ void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level 
 
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
+
+template <typename T>
+void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st);
 
 template <typename T>
 void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first,

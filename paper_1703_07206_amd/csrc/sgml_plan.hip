@@ -4,6 +4,7 @@
 #include "sgml.h"
 #include "sgml_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -25,6 +26,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kMaxCoarseOps = 4096;
 constexpr int kDefaultCoarseNodes = 5000;
+constexpr int kDefaultFuseMin = 1025;  // smallest 2D level (nodes per axis) visited in one fused pass
 
 struct Layout {
     size_t scal, ops, levels, s, e0, shat, sig0t;
@@ -244,7 +246,7 @@ struct HostOp {
 // the cycle's e at the end.
 template <typename T>
 const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev, const std::vector<int> &cnt,
-                       bool record, int coarse_level, bool fuse, std::vector<HostOp> &ops,
+                       bool record, int coarse_level, int fuse_min, std::vector<HostOp> &ops,
                        long long &updates_per_cycle)
 {
     const int n = P->n;
@@ -275,7 +277,9 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
         ops.push_back(h);
     };
     // visits of large 2D levels run as fused passes
-    auto fusable = [&](int nu) { return fuse && P->dim == 2 && nu < coarse_level && P->m(nu) >= 64; };
+    auto fusable = [&](int nu) {
+        return fuse_min > 0 && P->dim == 2 && nu < coarse_level && P->m(nu) >= fuse_min;
+    };
     for (int nu = 1; nu < n; ++nu) {
         E[nu][0] = P->at<T>(P->lay.e[nu][0]);
         E[nu][1] = P->at<T>(P->lay.e[nu][1]);
@@ -524,7 +528,8 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
         std::vector<HostOp> ops;
         long long updates_per_cycle = 0;
         const T *e = compile_cycle<T>(P, src0, lev, cnt, o->record_pres != 0,
-                                      coarse_level_of(P, o->coarse_nodes), o->fuse >= 0, ops,
+                                      coarse_level_of(P, o->coarse_nodes),
+                                      o->fuse < 0 ? 0 : (o->fuse == 0 ? kDefaultFuseMin : std::max(o->fuse, 64)), ops,
                                       updates_per_cycle);
         rc = upload_ops(P, ops, st);
         if (rc != SGML_OK) return rc;
@@ -544,8 +549,23 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             const int k_next = mixed ? std::ilogb(last) : 0;
             hipEvent_t *ev = o->profile ? prof_pair(P) : nullptr;
             if (ev) SGML_HIP(hipEventRecord(ev[0], st));
-            launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
-                               std::ldexp(1.0, -k_next), target(P, 0), st);
+            if (P->dim == 2 && o->fuse >= 0 && P->N >= 64) {
+                CycleEndArgs ca;
+                ca.e = e;
+                ca.escale = std::ldexp(1.0, k_cur);
+                ca.G = Gc;
+                ca.sigma = P->sigma;
+                ca.u = u;
+                ca.s = s;
+                ca.shat = shat;
+                ca.shat_scale = std::ldexp(1.0, -k_next);
+                ca.norm = target(P, 0);
+                ca.L = L0;
+                launch_cycle_end2d<T>(P->var, ca, st);
+            } else {
+                launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
+                                   std::ldexp(1.0, -k_next), target(P, 0), st);
+            }
             if (ev) {
                 SGML_HIP(hipEventRecord(ev[1], st));
                 timed.push_back({SGML_PROF_CYCLE_END, 0, ev});

@@ -22,26 +22,67 @@ namespace sgml {
 namespace {
 
 constexpr int kVisitBlock = 256;  // four independent wavefronts
-constexpr int kChunkRows = 64;
+constexpr int kChunkRows = 128;
 
+// Element idx of a level array through a 32-bit byte offset (2D levels are
+// below 4 GiB): a scalar base plus one per-lane register, no 64-bit address
+// arithmetic per lane.
 template <typename T>
-__device__ __forceinline__ T from_left(T v)  // value held by lane - 1
+__device__ __forceinline__ T ld(const T *base, unsigned idx)
 {
-    return __shfl_up(v, 1, 64);
+    return *(const T *)((const char *)base + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T *base, unsigned idx, T v)
+{
+    *(T *)((char *)base + idx * (unsigned)sizeof(T)) = v;
 }
 
-template <typename T>
-__device__ __forceinline__ T from_right(T v)  // value held by lane + 1
+// Whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane i
+// receives lane i-1's (from_left) or lane i+1's (from_right) value; the end
+// lanes, which have no source, receive 0 (they are halo lanes).  A few
+// cycles, no LDS crossbar.
+__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v)
 {
-    return __shfl_down(v, 1, 64);
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_from_left((int)(b & 0xffffffff)), hi = dpp_from_left((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+__device__ __forceinline__ double from_right(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_from_right((int)(b & 0xffffffff)), hi = dpp_from_right((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// theta / D with D the local diagonal: FP32 uses the hardware reciprocal
+// (the relaxation is the approximate inner solver of the mixed mode), FP64
+// divides.
+__device__ __forceinline__ float step_of(float theta, float D) { return theta * __builtin_amdgcn_rcpf(D); }
+__device__ __forceinline__ double step_of(double theta, double D) { return theta / D; }
+
+// Constants of one relaxation with a constant coefficient: the update
+// e + theta/D (dL e - g) with dL e = scale (sum of neighbours - W e) + a e and
+// D = W scale - a is the damped-Jacobi form
+//   e' = (1 - theta) e + beta * (sum of neighbours) - gamma * g,
+// beta = theta scale / D, gamma = theta / D (W = 4 axis, 6 radial: corners
+// weigh 1/2).  The residual dL e - g is formed only when it is recorded.
+template <typename T>
+struct RelaxK {
+    T scale, a, theta, omt, beta, gamma, aw;  // aw = a - W scale
+};
 
 // One relaxation of the node in the middle row of the window w (rows r-1,
-// r, r+1 of this lane's column); sg: the coefficient in the same rows.
-// All lanes must call it (cross-lane moves).
-template <typename T, int RAD, int SIG>
-__device__ __forceinline__ T relax(const T (&w)[3], const T (&sg)[3], T g, bool dir, T gval, T scale, T a,
-                                   T theta, T &resid)
+// r, r+1 of this lane's column); sg: the coefficient in the same rows.  All
+// lanes must call it (cross-lane moves).
+template <typename T, int RAD, int SIG, int REC>
+__device__ __forceinline__ T relax(const T (&w)[3], const T (&sg)[3], T g, bool dir, T gval, const RelaxK<T> &K,
+                                   T &resid)
 {
     const T c = w[1];
     const T ul = from_left(c), ur = from_right(c);
@@ -52,63 +93,88 @@ __device__ __forceinline__ T relax(const T (&w)[3], const T (&sg)[3], T g, bool 
         sl = from_left(w[2]);
         sr = from_right(w[2]);
     }
-    T acc1, acc2 = T(0), D;
     if (SIG) {
         const T sc = sg[1];
         const T tl = from_left(sc) + sc, tr = from_right(sc) + sc;
         const T tn = sg[0] + sc, ts = sg[2] + sc;
-        acc1 = tl * (ul - c) + tr * (ur - c) + tn * (w[0] - c) + ts * (w[2] - c);
-        T ds1 = tl + tr + tn + ts, ds2 = T(0);
+        T acc = tl * (ul - c) + tr * (ur - c) + tn * (w[0] - c) + ts * (w[2] - c);
+        T ds = tl + tr + tn + ts;
         if (RAD) {
             const T tnl = from_left(sg[0]) + sc, tnr = from_right(sg[0]) + sc;
             const T tsl = from_left(sg[2]) + sc, tsr = from_right(sg[2]) + sc;
-            acc2 = tnl * (nl - c) + tnr * (nr - c) + tsl * (sl - c) + tsr * (sr - c);
-            ds2 = tnl + tnr + tsl + tsr;
+            acc += T(0.5) * (tnl * (nl - c) + tnr * (nr - c) + tsl * (sl - c) + tsr * (sr - c));
+            ds += T(0.5) * (tnl + tnr + tsl + tsr);
         }
-        D = scale * T(0.5) * (ds1 + T(0.5) * ds2) - a;
-        acc1 = T(0.5) * (acc1 + T(0.5) * acc2);
-        acc2 = T(0);
-    } else {
-        acc1 = (ul - c) + (ur - c) + (w[0] - c) + (w[2] - c);
-        if (RAD) acc2 = (nl - c) + (nr - c) + (sl - c) + (sr - c);
-        D = scale * (RAD ? T(6) : T(4)) - a;
+        const T r = K.scale * T(0.5) * acc + K.a * c - g;
+        if (REC) resid = dir ? T(0) : r;
+        return dir ? gval : c + step_of(K.theta, K.scale * T(0.5) * ds - K.a) * r;
     }
-    const T Lu = scale * (acc1 + T(0.5) * acc2) + a * c;
-    const T r = Lu - g;
-    resid = dir ? T(0) : r;
-    return dir ? gval : c + (theta / D) * r;
+    T sum = (ul + ur) + (w[0] + w[2]);
+    if (RAD) sum += T(0.5) * ((nl + nr) + (sl + sr));
+    if (REC) resid = dir ? T(0) : K.scale * sum + K.aw * c - g;
+    return dir ? gval : K.omt * c + (K.beta * sum - K.gamma * g);
+}
+
+// The raw loads of one input row: the level's stale value, the source, the
+// coefficient and, for the interpolation, the next coarser level's values
+// and the stale values at its nodes (even columns only) in the coarse rows
+// Y = rm/2 and Y + 1 (odd rows).  Issued a few rows ahead of their use.
+template <typename T>
+struct RowIn {
+    T st, g, sg, c0, c1, s0, s1;
+};
+
+template <typename T, int PRO, int SIG>
+__device__ __forceinline__ void load_row(RowIn<T> &R, const VisitArgs &A, int xm, int rho, int m)
+{
+    // unsigned 32-bit element offsets (2D levels: m^2 < 2^31): a scalar base
+    // plus a per-lane offset, no 64-bit address arithmetic per lane
+    const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m, ux = (unsigned)xm;
+    const unsigned row = rm * um;
+    const T *__restrict__ estale = (const T *)A.estale;
+    R.st = (PRO && A.first) ? T(0) : ld(estale, row + ux);
+    R.g = ld((const T *)A.g, row + ux);
+    if (SIG) R.sg = ld((const T *)A.sig, row + ux);
+    if (PRO) {
+        const T *__restrict__ ec = (const T *)A.ecoarse;
+        const unsigned mc = (um + 1) >> 1, Y = rm >> 1;
+        R.c0 = R.c1 = R.s1 = T(0);
+        R.s0 = R.st;
+        if (!(ux & 1)) {
+            R.c0 = ld(ec, Y * mc + (ux >> 1));
+            if (rm & 1) {
+                R.c1 = ld(ec, (Y + 1) * mc + (ux >> 1));
+                if (!A.first) {
+                    R.s0 = ld(estale, 2 * Y * um + ux);
+                    R.s1 = ld(estale, (2 * Y + 2) * um + ux);
+                }
+            }
+        }
+    }
 }
 
 // The level's value at (rm, xm) with the pending variation of the next
-// coarser level interpolated (mc = (m + 1) / 2 nodes per axis there).  rm is
-// the same in every lane.  All lanes must call it (cross-lane moves).
+// coarser level interpolated: coarse nodes take the coarse value, the others
+// add the tensor-hat mean of the pending variation (coarse value minus stale
+// finer value) of the enclosing coarse nodes.  rm is the same in every lane;
+// all lanes must call it (cross-lane moves).
 template <typename T>
-__device__ __forceinline__ T prolonged(const T *__restrict__ estale, const T *__restrict__ ec, int first, int xm,
-                                       int rm, int m)
+__device__ __forceinline__ T prolonged(const RowIn<T> &R, int xm, int rm)
 {
-    const int mc = (m + 1) >> 1;
     const bool xe = !(xm & 1);
-    // pending variation of coarse row Y, interpolated along x to this column
-    auto pend = [&](int Y) -> T {
-        T p = T(0);
-        if (xe) {
-            p = ec[lin(xm >> 1, Y, 0, mc)];
-            if (!first) p -= estale[lin(xm, 2 * Y, 0, m)];
-        }
+    auto along_x = [&](T p) -> T {  // pending variation interpolated along x
         const T pl = from_left(p), pr = from_right(p);
         return xe ? p : T(0.5) * (pl + pr);
     };
-    const T st = first ? T(0) : estale[lin(xm, rm, 0, m)];
-    const int Y = rm >> 1;
     if (!(rm & 1)) {
-        const T p = pend(Y);
-        return xe ? ec[lin(xm >> 1, Y, 0, mc)] : st + p;
+        const T p = along_x(xe ? R.c0 - R.s0 : T(0));
+        return xe ? R.c0 : R.st + p;
     }
-    const T p0 = pend(Y), p1 = pend(Y + 1);
-    return st + T(0.5) * (p0 + p1);
+    const T p0 = along_x(xe ? R.c0 - R.s0 : T(0)), p1 = along_x(xe ? R.c1 - R.s1 : T(0));
+    return R.st + T(0.5) * (p0 + p1);
 }
 
-template <typename T, int RAD, int SIG, int S, int PRO, int INJ>
+template <typename T, int RAD, int SIG, int S, int PRO, int REC>
 __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
 {
     constexpr int HX = S + PRO;     // halo columns on each side of a strip
@@ -117,7 +183,8 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     const int m = L.m;
     const int lane = threadIdx.x & 63;
     const int strips = (m + W - 1) / W;
-    const int wid = blockIdx.x * (kVisitBlock / 64) + (threadIdx.x >> 6);
+    // wavefront index, known to be uniform: row and strip arithmetic stays scalar
+    const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sx = wid % strips, sy = wid / strips;
     const int y0 = sy * kChunkRows;
     if (y0 >= m) return;  // the whole wavefront: past the last chunk
@@ -126,13 +193,24 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     const int xm = mir(x, m);
     const bool xout = lane >= HX && lane < HX + W && x < m;
 
-    const T *__restrict__ estale = (const T *)A.estale;
-    const T *__restrict__ ec = (const T *)A.ecoarse;
-    const T *__restrict__ g = (const T *)A.g;
-    const T *__restrict__ sig = (const T *)A.sig;
     T *__restrict__ eout = (T *)A.eout;
     T *__restrict__ einj = (T *)A.einj;
-    const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
+    RelaxK<T> K;
+    K.scale = (T)L.scale;
+    K.a = (T)L.a;
+    K.theta = (T)L.theta;
+    {
+        const double W = RAD ? 6.0 : 4.0, D = W * L.scale - L.a;
+        K.omt = (T)(1.0 - L.theta);
+        K.beta = (T)(L.theta * L.scale / D);
+        K.gamma = (T)(L.theta / D);
+        K.aw = (T)(L.a - W * L.scale);
+    }
+    const bool inject = A.inject != 0;
+    // Dirichlet faces: the x part is fixed per lane, the y part per row
+    const bool xdir = ((L.dir & 1u) && xm == 0) || ((L.dir & 2u) && xm == m - 1);
+    const double *__restrict__ G = A.G;
+    const int glane = xm * L.lam, gpitch = L.lam * L.N;
 
     T w[S][3];
     T gh[S + 1];  // gh[k]: source at input row - k
@@ -149,18 +227,19 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     for (int k = 0; k < S + 2; ++k) sh[k] = T(1);
 
     const int rows = (y1 - y0) + 2 * S;
-    for (int t = 0; t < rows; ++t) {
+    // one input row through the pipeline: the prolonged value enters
+    // relaxation 1, each relaxation's output row enters the next one
+    auto step_row = [&](const RowIn<T> &R, int t) {
         const int rho = y0 - S + t;  // input row, outside the grid: its image
         const int rm = mir(rho, m);
-        const size_t q = lin(xm, rm, 0, m);
-        T val = PRO ? prolonged<T>(estale, ec, A.first, xm, rm, m) : estale[q];
+        T val = PRO ? prolonged<T>(R, xm, rm) : R.st;
 #pragma unroll
         for (int k = S; k > 0; --k) gh[k] = gh[k - 1];
-        gh[0] = g[q];
+        gh[0] = R.g;
         if (SIG) {
 #pragma unroll
             for (int k = S + 1; k > 0; --k) sh[k] = sh[k - 1];
-            sh[0] = sig[q];
+            sh[0] = R.sg;
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -169,25 +248,48 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
             w[s][2] = val;
             const int r = rho - s - 1;  // row relaxation s+1 produces now
             const int rmr = mir(r, m);
-            const bool dir = is_dir<2>(xm, rmr, 0, m, L.dir);
-            const T gval = (dir && A.G) ? (T)A.G[lin(xm * L.lam, rmr * L.lam, 0, L.N)] : T(0);
+            const bool ydir = ((L.dir & 4u) && rmr == 0) || ((L.dir & 8u) && rmr == m - 1);
+            const bool dir = xdir || ydir;
+            T gval = T(0);
+            if (G) gval = dir ? (T)ld(G, (unsigned)rmr * (unsigned)gpitch + (unsigned)glane) : T(0);
             const T sg[3] = {sh[s + 2], sh[s + 1], sh[s]};
-            T resid;
-            val = relax<T, RAD, SIG>(w[s], sg, gh[s + 1], dir, gval, scale, a, theta, resid);
-            if (A.pres[s] >= 0 && r >= y0 && r < y1 && xout) {
+            T resid = T(0);
+            val = relax<T, RAD, SIG, REC>(w[s], sg, gh[s + 1], dir, gval, K, resid);
+            if (REC && A.pres[s] >= 0 && r >= y0 && r < y1 && xout) {
                 const unsigned long long b = dbits((double)resid);
                 pr[s] = b > pr[s] ? b : pr[s];
             }
         }
         const int ro = rho - S;
         if (ro >= y0 && ro < y1 && xout) {
-            eout[lin(x, ro, 0, m)] = val;
-            if (INJ && !(ro & 1) && !(x & 1)) einj[lin(x >> 1, ro >> 1, 0, (m + 1) >> 1)] = val;
+            st(eout, (unsigned)ro * (unsigned)m + (unsigned)x, val);
+            if (inject && !(ro & 1) && !(x & 1))
+                st(einj, (unsigned)(ro >> 1) * (unsigned)((m + 1) >> 1) + (unsigned)(x >> 1), val);
         }
+    };
+    // raw loads in batches of B rows, one batch in flight while the other is
+    // consumed (the unrolled batches turn the window shifts into renames)
+    constexpr int B = 3;
+    RowIn<T> qa[B], qb[B];
+    auto load_batch = [&](RowIn<T>(&q)[B], int t0) {
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + k < rows) load_row<T, PRO, SIG>(q[k], A, xm, y0 - S + t0 + k, m);
+    };
+    load_batch(qa, 0);
+    for (int t0 = 0; t0 < rows; t0 += 2 * B) {
+        load_batch(qb, t0 + B);
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + k < rows) step_row(qa[k], t0 + k);
+        load_batch(qa, t0 + 2 * B);
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + B + k < rows) step_row(qb[k], t0 + B + k);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (A.pres[s] < 0) continue;
+        if (!REC || A.pres[s] < 0) continue;
         unsigned long long v = pr[s];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -199,24 +301,159 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     }
 }
 
-template <typename T, int RAD, int SIG, int S, int PRO, int INJ>
+// End of a cycle on a 2D level 0 (the recurrence of Sec. 2, FP64): u += e,
+// s -= dL_1 e at unknowns (s = 0 at Dirichlet nodes), next cycle's source
+// shat = s * shat_scale, and max |s|.  e is escale * E with E's Dirichlet
+// values replaced by G (first cycle) or 0.  Same strip/row marching as the
+// visit: e is read once per node, its vertical neighbours come from a
+// three-row window and the horizontal ones from the adjacent lanes.
+template <typename T, int RAD, int SIG>
+__global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
+{
+    constexpr int HX = 1;
+    constexpr int W = 64 - 2 * HX;
+    const Level L = A.L;
+    const int m = L.m;
+    const int lane = threadIdx.x & 63;
+    const int strips = (m + W - 1) / W;
+    // wavefront index, known to be uniform: row and strip arithmetic stays scalar
+    const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = wid % strips, sy = wid / strips;
+    const int y0 = sy * kChunkRows;
+    if (y0 >= m) return;
+    const int y1 = min(m, y0 + kChunkRows);
+    const int x = sx * W - HX + lane;
+    const int xm = mir(x, m);
+    const bool xout = lane >= HX && lane < HX + W && x < m;
+    const bool xdir = ((L.dir & 1u) && xm == 0) || ((L.dir & 2u) && xm == m - 1);
+    const T *__restrict__ E = (const T *)A.e;
+    const double *__restrict__ G = A.G;
+    const double *__restrict__ sig = A.sigma;
+    double *__restrict__ u = A.u;
+    double *__restrict__ sres = A.s;
+    T *__restrict__ shat = (T *)A.shat;
+    const double scale = L.scale, a = L.a, escale = A.escale;
+
+    const int rows = (y1 - y0) + 2;
+    double w[3] = {0.0, 0.0, 0.0}, sw[3] = {1.0, 1.0, 1.0};
+    unsigned long long nb = 0;
+    // raw loads of input row rho (e, coefficient) and of output row rho - 1 (s, u)
+    struct Raw {
+        T e;
+        double sg, s, u;
+    };
+    auto load = [&](Raw &R, int t) {
+        const int rho = y0 - 1 + t;
+        const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m;
+        R.e = ld(E, rm * um + (unsigned)xm);
+        if (SIG) R.sg = ld(sig, rm * um + (unsigned)xm);
+        const int r = rho - 1;
+        if (r >= y0 && r < y1 && xout) {
+            R.s = ld((const double *)sres, (unsigned)r * um + (unsigned)x);
+            R.u = ld((const double *)u, (unsigned)r * um + (unsigned)x);
+        }
+    };
+    auto step_row = [&](const Raw &R, int t) {
+        const int rho = y0 - 1 + t, rm = mir(rho, m);
+        const bool ydir_in = ((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1);
+        double ev = escale * (double)R.e;
+        if (xdir || ydir_in) ev = G ? ld(G, (unsigned)rm * (unsigned)m + (unsigned)xm) : 0.0;  // Dirichlet values
+        w[0] = w[1];
+        w[1] = w[2];
+        w[2] = ev;
+        if (SIG) {
+            sw[0] = sw[1];
+            sw[1] = sw[2];
+            sw[2] = R.sg;
+        }
+        const int r = rho - 1;
+        // dL_1 e at row r (all lanes: cross-lane moves)
+        const double c = w[1];
+        const double ul = from_left(c), ur = from_right(c);
+        double Le;
+        if (SIG) {
+            const double sc = sw[1];
+            const double tl = from_left(sc) + sc, tr = from_right(sc) + sc, tn = sw[0] + sc, ts = sw[2] + sc;
+            double acc = tl * (ul - c) + tr * (ur - c) + tn * (w[0] - c) + ts * (w[2] - c);
+            if (RAD) {
+                const double nl = from_left(w[0]), nr = from_right(w[0]), sl = from_left(w[2]),
+                             sr = from_right(w[2]);
+                const double tnl = from_left(sw[0]) + sc, tnr = from_right(sw[0]) + sc;
+                const double tsl = from_left(sw[2]) + sc, tsr = from_right(sw[2]) + sc;
+                acc += 0.5 * (tnl * (nl - c) + tnr * (nr - c) + tsl * (sl - c) + tsr * (sr - c));
+            }
+            Le = 0.5 * scale * acc + a * c;
+        } else {
+            double acc = (ul - c) + (ur - c) + (w[0] - c) + (w[2] - c);
+            if (RAD) {
+                const double nl = from_left(w[0]), nr = from_right(w[0]), sl = from_left(w[2]),
+                             sr = from_right(w[2]);
+                acc += 0.5 * ((nl - c) + (nr - c) + (sl - c) + (sr - c));
+            }
+            Le = scale * acc + a * c;
+        }
+        if (t >= 2 && r >= y0 && r < y1 && xout) {
+            const bool ydir = ((L.dir & 4u) && r == 0) || ((L.dir & 8u) && r == m - 1);
+            const unsigned q = (unsigned)r * (unsigned)m + (unsigned)x;
+            st(u, q, R.u + c);
+            if (xdir || ydir) {
+                st(sres, q, 0.0);
+                if (shat) st(shat, q, T(0));
+            } else {
+                const double snew = R.s - Le;
+                st(sres, q, snew);
+                if (shat) st(shat, q, (T)(snew * A.shat_scale));
+                const unsigned long long b = dbits(snew);
+                nb = b > nb ? b : nb;
+            }
+        }
+    };
+    constexpr int B = 3;
+    Raw qa[B], qb[B];
+    auto load_batch = [&](Raw(&q)[B], int t0) {
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + k < rows) load(q[k], t0 + k);
+    };
+    load_batch(qa, 0);
+    for (int t0 = 0; t0 < rows; t0 += 2 * B) {
+        load_batch(qb, t0 + B);
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + k < rows) step_row(qa[k], t0 + k);
+        load_batch(qa, t0 + 2 * B);
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + B + k < rows) step_row(qb[k], t0 + B + k);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(nb, off, 64);
+        nb = o > nb ? o : nb;
+    }
+    if (lane == 0 && nb) atomicMax(A.norm + (size_t)(wid % kRedSlots) * kRedStride, nb);
+}
+
+template <typename T, int RAD, int SIG, int S, int PRO, int REC>
 void launch_one(const VisitArgs &a, hipStream_t st)
 {
     constexpr int W = 64 - 2 * (S + PRO);
     const int m = a.L.m;
     const long long waves = (long long)((m + W - 1) / W) * ((m + kChunkRows - 1) / kChunkRows);
     const unsigned blocks = (unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64));
-    hipLaunchKernelGGL((k_visit2d<T, RAD, SIG, S, PRO, INJ>), dim3(blocks), dim3(kVisitBlock), 0, st, a);
+    hipLaunchKernelGGL((k_visit2d<T, RAD, SIG, S, PRO, REC>), dim3(blocks), dim3(kVisitBlock), 0, st, a);
 }
 
 template <typename T, int RAD, int SIG, int S>
 void launch_s(const VisitArgs &a, hipStream_t st)
 {
-    if (a.prolong && a.inject)
+    bool rec = false;
+    for (int k = 0; k < a.sweeps; ++k) rec = rec || a.pres[k] >= 0;
+    if (a.prolong && rec)
         launch_one<T, RAD, SIG, S, 1, 1>(a, st);
     else if (a.prolong)
         launch_one<T, RAD, SIG, S, 1, 0>(a, st);
-    else if (a.inject)
+    else if (rec)
         launch_one<T, RAD, SIG, S, 0, 1>(a, st);
     else
         launch_one<T, RAD, SIG, S, 0, 0>(a, st);
@@ -236,6 +473,25 @@ void launch_rs(const VisitArgs &a, hipStream_t st)
 }  // namespace
 
 bool fused_visit_supported(int sweeps) { return sweeps == 1 || sweeps == 2 || sweeps == 4 || sweeps == 6; }
+
+template <typename T>
+void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
+{
+    const int m = a.L.m;
+    const long long waves = (long long)((m + 61) / 62) * ((m + kChunkRows - 1) / kChunkRows);
+    const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
+    if (v.radial && v.sigma)
+        hipLaunchKernelGGL((k_cycle_end2d<T, 1, 1>), grid, block, 0, st, a);
+    else if (v.radial)
+        hipLaunchKernelGGL((k_cycle_end2d<T, 1, 0>), grid, block, 0, st, a);
+    else if (v.sigma)
+        hipLaunchKernelGGL((k_cycle_end2d<T, 0, 1>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_cycle_end2d<T, 0, 0>), grid, block, 0, st, a);
+}
+
+template void launch_cycle_end2d<double>(const Variant &, const CycleEndArgs &, hipStream_t);
+template void launch_cycle_end2d<float>(const Variant &, const CycleEndArgs &, hipStream_t);
 
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st)

@@ -248,7 +248,7 @@ def test_fused_visits_match_oracle(case, n_r, sched):
     P = oracle_problem(wl)
     u_or, info = P.solve(wl.f, G=wl.G, tol=0.0, max_cycles=2, n_r=n_r, reading=sched)
     _, pres_or = P.cycle(wl.f, G=wl.G, n_r=n_r, reading=sched, with_pres=True)
-    for fuse in (0, -1):
+    for fuse in (64, -1):
         u, st = gpu_solve(wl, tol=0.0, max_cycles=2, n_r=n_r, schedule=sched, fuse=fuse)
         assert rel_inf(u, u_or) < 1e-12, (fuse, rel_inf(u, u_or))
         um, _ = gpu_solve(wl, "mixed", tol=0.0, max_cycles=2, n_r=n_r, schedule=sched, fuse=fuse)
@@ -264,6 +264,6 @@ def test_fused_visits_converged(case):
     wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1300 + n)
     u_or, _ = oracle_problem(wl).solve(wl.f, G=wl.G, tol=1e-15, max_cycles=200)
     for prec, tol in (("fp64", 1e-15), ("mixed", 1e-14)):
-        u, st = gpu_solve(wl, prec, tol=tol, max_cycles=200)
+        u, st = gpu_solve(wl, prec, tol=tol, max_cycles=200, fuse=64)
         assert st["status"] == 0
         assert rel_inf(u, u_or) < 1e-12

@@ -8,8 +8,10 @@ precision solve (FP32 cycle, FP64 refinement); the plain FP64 solve of the
 same workload is timed beside it.  Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,7 +32,47 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="poisson2d_blobs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of 1 GiB, three times: FETCH_SIZE / WRITE_SIZE of these
+    dispatches against the known 1 GiB give the counters' scale."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+
+
+def kernel_source_hash():
+    src = os.path.join(ROOT, "paper_1703_07206_amd", "csrc", "sgml_visit2d.hip")
+    with open(src, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, nodes):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_*.md), scaled by the copy calibration; None when the
+    summary is missing or was taken on another version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_visit2d_poisson2d_blobs_4097.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256_16") != kernel_source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    fetch = k["fetch_kib"] * 1024 * rec["fetch_scale"]
+    write = k["write_kib"] * 1024 * rec["write_scale"]
+    return {"bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "bytes_per_node": (fetch + write) / nodes}
 
 
 def timed_solves(plan, f, G, u, precision, steps, profile):
@@ -62,6 +104,9 @@ def cpu_baseline(wl, cycles):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not part of this build", file=sys.stderr)
@@ -116,6 +161,7 @@ def main():
     achieved = k_mix[dom]["GBs"]
     bytes_per_launch = k_mix[dom]["bytes_per_node"] * wl.nodes
 
+    traffic = measured_traffic(dom, wl.nodes) if args.workload == "poisson2d_blobs" else None
     out = {
         "metric": METRIC,
         "value": wl.nodes / t_mix / 1e9,
@@ -137,7 +183,9 @@ def main():
         "mixed": {"cycles": sm["cycles"], "relres": sm["relres"], "relres_true": r_mix / norm0,
                   "rel_diff_vs_fp64": diff, "kernels": k_mix},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_detail": traffic,
                      "kernel": f"level-0 {dom} (FP32, 5-point)",
                      "bytes_per_launch": bytes_per_launch},
     }

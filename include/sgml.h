@@ -103,8 +103,9 @@ typedef struct {
     int fuse;         /* 2D levels with at least this many nodes per axis (and
                          too large for the coarse kernel) run each visit as one
                          fused pass; 0: default (1025), < 0: never (one launch per
-                         interpolation, relaxation and injection); values
-                         below 64 act as 64 */
+                         interpolation, relaxation and injection, and the
+                         generic relaxation and cycle-end kernels in 2D and 3D);
+                         values below 64 act as 64 */
 } sgml_opts;
 
 #define SGML_HIST 512

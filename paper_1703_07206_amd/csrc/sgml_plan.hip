@@ -420,7 +420,7 @@ sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, hipStream_t st)
 // the rest as grid launches; level-0 relaxations timed when profiling.
 template <typename T>
 sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *G, bool profile,
-                    std::vector<Timed> &timed, hipStream_t st)
+                    bool use_sweep3d, std::vector<Timed> &timed, hipStream_t st)
 {
     const CoarseOp *dev_ops = P->at<CoarseOp>(P->lay.ops);
     const Level *dev_levels = P->at<Level>(P->lay.levels);
@@ -470,8 +470,13 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
         default: {
             hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
             if (ev) SGML_HIP(hipEventRecord(ev[0], st));
-            launch_sweep<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1,
-                            (const T *)o.in2, G, o.target >= 0 ? target(P, o.target) : nullptr, st);
+            unsigned long long *tg = o.target >= 0 ? target(P, o.target) : nullptr;
+            if (P->dim == 3 && use_sweep3d && sweep3d_supported(o.m))
+                launch_sweep3d<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1,
+                                  (const T *)o.in2, G, tg, st);
+            else
+                launch_sweep<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1,
+                                (const T *)o.in2, G, tg, st);
             if (ev) {
                 SGML_HIP(hipEventRecord(ev[1], st));
                 timed.push_back({SGML_PROF_SWEEP0, 1, ev});
@@ -542,7 +547,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
             std::vector<Timed> timed;
             P->pev_used = 0;
-            rc = run_ops<T>(P, ops, Gc, o->profile != 0, timed, st);
+            rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, timed, st);
             if (rc != SGML_OK) return rc;
             S.node_updates += updates_per_cycle;
             // next cycle's scaling from the last known residual norm (lagged)

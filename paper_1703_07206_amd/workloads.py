@@ -21,6 +21,9 @@ Helmholtz-Poisson examples):
 ``helmholtz3d_adjoint`` 129^3, same medium, f = U(-1,1), loss target u_t
 ``poisson3d_charges``   513^3, radial 27-point, Dirichlet 0, 256 Gaussian
                      point charges of width 2h plus 1e-3 U(-1,1) noise
+``capacitor_tanh``   129^3, the heterogeneous Laplace problem of Sec. 3.4:
+                     sigma = 0.55 +/- 0.45 tanh((r - 0.2)/0.1) (eq. 16), u = +1 on
+                     the top and -1 on the bottom face, Neumann lateral faces
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -176,6 +179,22 @@ def poisson3d_charges(n=9, seed=5, ncharges=256, noise=1e-3, cutoff=8.0):
                     extra=dict(u_target=ut))
 
 
+def capacitor_tanh(n=7, sign=+1):
+    """Sec. 3.4: div(sigma grad u) = 0 (eq. 15) with the spherical
+    coefficient of eq. 16 centred in the cube, u = -1 / +1 on the bottom /
+    top (z = 0 / z = 1) faces and zero normal derivative on the lateral
+    faces.  No random draws."""
+    N = 2 ** n + 1
+    Z, Y, X = coords(n, 3)
+    r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2)
+    sigma = 0.55 + sign * 0.45 * np.tanh((r - 0.2) / 0.1)
+    G = np.zeros((N, N, N))
+    G[0] = -1.0
+    G[-1] = 1.0
+    return Workload("capacitor_tanh", 3, n, RADIAL, "NNNNDD", 0.0, np.zeros((N, N, N)), sigma=sigma, G=G,
+                    extra=dict(sign=sign))
+
+
 def random_problem(dim, n, stencil, faces, seed, hetero=True, a=0.0, dirichlet_values=True):
     """Small generic problem for parity tests: random source, smooth positive
     coefficient with random contrast, random Dirichlet values."""
@@ -193,4 +212,5 @@ CONFIGS = {
     "helmholtz3d_spheres": helmholtz3d_spheres,
     "helmholtz3d_adjoint": helmholtz3d_adjoint,
     "poisson3d_charges": poisson3d_charges,
+    "capacitor_tanh": capacitor_tanh,
 }

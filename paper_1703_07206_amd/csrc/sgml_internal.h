@@ -107,8 +107,11 @@ void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st);
 
-// One relaxation of a 3D level (m >= 33) marching in z through LDS planes.
+// One relaxation / the cycle-end pass of a 3D level (m >= 33) marching in z
+// through LDS planes.
 bool sweep3d_supported(int m);
+template <typename T>
+void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st);
 template <typename T>
 void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
                     const double *G, unsigned long long *pres, hipStream_t st);

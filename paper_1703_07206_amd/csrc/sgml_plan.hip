@@ -554,7 +554,8 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             const int k_next = mixed ? std::ilogb(last) : 0;
             hipEvent_t *ev = o->profile ? prof_pair(P) : nullptr;
             if (ev) SGML_HIP(hipEventRecord(ev[0], st));
-            if (P->dim == 2 && o->fuse >= 0 && P->N >= 64) {
+            const bool z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N);
+            if ((P->dim == 2 && o->fuse >= 0 && P->N >= 64) || z_march) {
                 CycleEndArgs ca;
                 ca.e = e;
                 ca.escale = std::ldexp(1.0, k_cur);
@@ -566,7 +567,10 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                 ca.shat_scale = std::ldexp(1.0, -k_next);
                 ca.norm = target(P, 0);
                 ca.L = L0;
-                launch_cycle_end2d<T>(P->var, ca, st);
+                if (z_march)
+                    launch_cycle_end3d<T>(P->var, ca, st);
+                else
+                    launch_cycle_end2d<T>(P->var, ca, st);
             } else {
                 launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
                                    std::ldexp(1.0, -k_next), target(P, 0), st);

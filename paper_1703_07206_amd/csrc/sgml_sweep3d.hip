@@ -113,9 +113,120 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
     }
 }
 
+// End of a cycle on a 3D level 0 (recurrence of Sec. 2, FP64), marching in
+// z like k_sweep3d: e = escale * E with Dirichlet values replaced by G (first
+// cycle) or 0 is staged per plane in LDS, then u += e, s -= dL_1 e at
+// unknowns (s = 0 at Dirichlet nodes), shat = s * shat_scale, max |s|.
+template <typename T, int RAD, int SIG>
+__global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
+{
+    __shared__ double se[3][PY][PX];
+    __shared__ double ss[SIG ? 3 : 1][SIG ? PY : 1][SIG ? PX : 1];
+    const Level L = A.L;
+    const int m = L.m;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
+    const int z1 = min(m, z0 + ZC);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < m && y < m;
+    const size_t plane = (size_t)m * m;
+    const T *__restrict__ E = (const T *)A.e;
+    const double *__restrict__ G = A.G;
+    const double *__restrict__ sig = A.sigma;
+    T *__restrict__ shat = (T *)A.shat;
+
+    auto stage = [&](int slot, int zz) {
+        const int zm = mir(zz, m);
+        const size_t zoff = (size_t)zm * plane;
+        for (int idx = threadIdx.x; idx < PX * PY; idx += kThreads) {
+            const int ly = idx / PX, lx = idx % PX;
+            const int ym = mir(y0 - 1 + ly, m), xm = mir(x0 - 1 + lx, m);
+            const size_t q = zoff + (size_t)ym * m + xm;
+            double v = A.escale * (double)E[q];
+            if (is_dir<3>(xm, ym, zm, m, L.dir)) v = G ? G[q] : 0.0;
+            se[slot][ly][lx] = v;
+            if (SIG) ss[slot][ly][lx] = sig[q];
+        }
+    };
+    unsigned long long nb = 0;
+    stage(0, z0 - 1);
+    stage(1, z0);
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;
+        const int sm = k % 3, sc = (k + 1) % 3, sp = (k + 2) % 3;
+        stage(sp, z + 1);
+        __syncthreads();
+        if (own) {
+            const size_t c = (size_t)z * plane + (size_t)y * m + x;
+            const double ec = se[sc][ty + 1][tx + 1];
+            A.u[c] += ec;
+            if (is_dir<3>(x, y, z, m, L.dir)) {
+                A.s[c] = 0.0;
+                if (shat) shat[c] = T(0);
+            } else {
+                const int slots[3] = {sm, sc, sp};
+                const double sgc = SIG ? ss[sc][ty + 1][tx + 1] : 1.0;
+                double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+                            if (cls == 0 || (!RAD && cls != 1)) continue;
+                            const int sl = slots[dz + 1];
+                            const double du = se[sl][ty + 1 + dy][tx + 1 + dx] - ec;
+                            if (SIG)
+                                acc[cls - 1] += (ss[sl][ty + 1 + dy][tx + 1 + dx] + sgc) * du;
+                            else
+                                acc[cls - 1] += du;
+                        }
+                    }
+                }
+                const double sw = acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2];
+                const double Le = (SIG ? 0.5 * L.scale * sw : L.scale * sw) + L.a * ec;
+                const double sn = A.s[c] - Le;
+                A.s[c] = sn;
+                if (shat) shat[c] = (T)(sn * A.shat_scale);
+                const unsigned long long b = dbits(sn);
+                nb = b > nb ? b : nb;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(nb, off, 64);
+        nb = o > nb ? o : nb;
+    }
+    if ((threadIdx.x & 63) == 0 && nb) {
+        const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z) + threadIdx.x / 64;
+        atomicMax(A.norm + (b % kRedSlots) * kRedStride, nb);
+    }
+}
+
 }  // namespace
 
 bool sweep3d_supported(int m) { return m >= 33; }
+
+template <typename T>
+void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
+{
+    const int m = a.L.m;
+    const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + ZC - 1) / ZC), block(kThreads);
+    if (v.radial && v.sigma)
+        hipLaunchKernelGGL((k_cycle_end3d<T, 1, 1>), grid, block, 0, st, a);
+    else if (v.radial)
+        hipLaunchKernelGGL((k_cycle_end3d<T, 1, 0>), grid, block, 0, st, a);
+    else if (v.sigma)
+        hipLaunchKernelGGL((k_cycle_end3d<T, 0, 1>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_cycle_end3d<T, 0, 0>), grid, block, 0, st, a);
+}
+
+template void launch_cycle_end3d<double>(const Variant &, const CycleEndArgs &, hipStream_t);
+template void launch_cycle_end3d<float>(const Variant &, const CycleEndArgs &, hipStream_t);
 
 template <typename T>
 void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,

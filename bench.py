@@ -81,7 +81,8 @@ def timed_solves(plan, f, G, u, precision, steps, profile):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, st = plan.solve(f, G, u, tol=TOL, max_cycles=200, precision=precision, profile=profile)
+        _, st = plan.solve(f, G, u, tol=TOL, max_cycles=2000, precision=precision, profile=profile,
+                           stall_window=-1)
         stats.append(st)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, stats
@@ -123,8 +124,8 @@ def main():
     u64 = torch.empty_like(f)
 
     for _ in range(args.warmup):
-        plan.solve(f, G, u, tol=TOL, max_cycles=200, precision=sgml.MIXED)
-        plan.solve(f, G, u64, tol=TOL, max_cycles=200, precision=sgml.FP64)
+        plan.solve(f, G, u, tol=TOL, max_cycles=2000, precision=sgml.MIXED, stall_window=-1)
+        plan.solve(f, G, u64, tol=TOL, max_cycles=2000, precision=sgml.FP64, stall_window=-1)
     t_mix, st_mix = timed_solves(plan, f, G, u, sgml.MIXED, args.steps, True)
     t_64, st_64 = timed_solves(plan, f, G, u64, sgml.FP64, args.steps, True)
     print(f"# mixed: {t_mix * 1e3:.3f} ms/solve, {st_mix[-1]['cycles']} cycles; "

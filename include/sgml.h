@@ -106,6 +106,9 @@ typedef struct {
                          interpolation, relaxation and injection, and the
                          generic relaxation and cycle-end kernels in 2D and 3D);
                          values below 64 act as 64 */
+    int chunk_rows;   /* rows each wavefront marches through in the 2D fused passes;
+                         0: chosen per launch (16, or 32 for long fused visits of
+                         large levels), values below 8 act as 8 */
 } sgml_opts;
 
 #define SGML_HIST 512

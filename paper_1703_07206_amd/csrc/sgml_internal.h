@@ -73,6 +73,7 @@ struct VisitArgs {
     int sweeps;           // 1 .. kMaxFusedSweeps
     int prolong, inject;  // prologue / epilogue present
     int pres[kMaxFusedSweeps];  // reduction target per relaxation, -1 for none
+    int chunk;            // rows per wavefront
 };
 bool fused_visit_supported(int sweeps);
 
@@ -87,6 +88,7 @@ struct CycleEndArgs {
     double shat_scale;
     unsigned long long *norm;  // reduction target of max |s|
     Level L;
+    int chunk;            // rows per wavefront (2D)
 };
 
 // Precision-generic launchers (T = double or float); all enqueue on `st`.

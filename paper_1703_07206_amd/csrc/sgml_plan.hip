@@ -420,7 +420,7 @@ sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, hipStream_t st)
 // the rest as grid launches; level-0 relaxations timed when profiling.
 template <typename T>
 sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *G, bool profile,
-                    bool use_sweep3d, std::vector<Timed> &timed, hipStream_t st)
+                    bool use_sweep3d, int chunk, std::vector<Timed> &timed, hipStream_t st)
 {
     const CoarseOp *dev_ops = P->at<CoarseOp>(P->lay.ops);
     const Level *dev_levels = P->at<Level>(P->lay.levels);
@@ -439,6 +439,7 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
         const CoarseOp &o = ops[i].op;
         if (o.kind == kOpVisit) {
             VisitArgs a = ops[i].visit;
+            a.chunk = chunk;
             a.G = G;
             a.targets = targets;
             a.L = P->level(o.level);
@@ -538,6 +539,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                                       updates_per_cycle);
         rc = upload_ops(P, ops, st);
         if (rc != SGML_OK) return rc;
+        const int chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
         int k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
         if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
         double last = norm0;
@@ -547,7 +549,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
             std::vector<Timed> timed;
             P->pev_used = 0;
-            rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, timed, st);
+            rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, timed, st);
             if (rc != SGML_OK) return rc;
             S.node_updates += updates_per_cycle;
             // next cycle's scaling from the last known residual norm (lagged)
@@ -567,6 +569,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                 ca.shat_scale = std::ldexp(1.0, -k_next);
                 ca.norm = target(P, 0);
                 ca.L = L0;
+                ca.chunk = chunk;
                 if (z_march)
                     launch_cycle_end3d<T>(P->var, ca, st);
                 else

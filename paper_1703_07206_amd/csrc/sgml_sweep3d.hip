@@ -5,8 +5,10 @@
 // with a one-node halo, in a ring of three LDS planes; a node's 26 (radial)
 // or 6 (axis) neighbours are then read from LDS instead of from L1/L2, and
 // every value crosses the memory hierarchy about once.  Halo cells outside
-// the grid hold the image node, so Neumann faces need no special case.
-// Same arithmetic per node as the generic relaxation (k_sweep).
+// the grid hold the image node, so Neumann faces need no special case.  With
+// a constant coefficient the 26 neighbours are summed by class from per-plane
+// partial sums (face and corner neighbours within a plane), 8 LDS reads per
+// node instead of 26.
 #include "sgml_device.h"
 
 namespace sgml {
@@ -16,6 +18,11 @@ namespace {
 constexpr int TX = 64, TY = 8, ZC = 16;  // tile and z chunk
 constexpr int kThreads = TX * TY;
 constexpr int PX = TX + 2, PY = TY + 2;  // staged plane with halo
+
+// theta / D: the hardware reciprocal in FP32 (the mixed mode's approximate
+// inner solver), a division in FP64.
+__device__ __forceinline__ float step_of3(float theta, float D) { return theta * __builtin_amdgcn_rcpf(D); }
+__device__ __forceinline__ double step_of3(double theta, double D) { return theta / D; }
 
 template <typename T, int RAD, int SIG>
 __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein, T *__restrict__ eout,
@@ -43,22 +50,61 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
         }
     };
     const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
+    // constant coefficient: D is the same everywhere
+    const T Wc = RAD ? T(6) + T(0.5) * T(12) + T(1.0 / 3.0) * T(8) : T(6);
+    const T tD = theta / (scale * Wc - a);
     unsigned long long rb = 0;
+    // constant coefficient: per plane and column, the centre value, the sum
+    // of the 4 in-plane face neighbours and of the 4 in-plane corners; the
+    // 26 neighbours of the middle plane's node are classes of these sums
+    T cc[3] = {T(0), T(0), T(0)}, cx[3] = {T(0), T(0), T(0)}, ck[3] = {T(0), T(0), T(0)};
+    auto plane_sums = [&](int slot, int at) {
+        cc[at] = su[slot][ty + 1][tx + 1];
+        cx[at] = (su[slot][ty + 1][tx] + su[slot][ty + 1][tx + 2]) + (su[slot][ty][tx + 1] + su[slot][ty + 2][tx + 1]);
+        if (RAD)
+            ck[at] = (su[slot][ty][tx] + su[slot][ty][tx + 2]) + (su[slot][ty + 2][tx] + su[slot][ty + 2][tx + 2]);
+    };
     stage(0, z0 - 1);
     stage(1, z0);
+    if (!SIG) {
+        __syncthreads();
+        plane_sums(0, 1);  // at = 1: plane z-1 of the first node, shifted in below
+        plane_sums(1, 2);
+    }
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
         const int sm = k % 3, sc = (k + 1) % 3, sp = (k + 2) % 3;  // planes z-1, z, z+1
         stage(sp, z + 1);
         __syncthreads();
+        if (!SIG) {
+            cc[0] = cc[1], cc[1] = cc[2];
+            cx[0] = cx[1], cx[1] = cx[2];
+            ck[0] = ck[1], ck[1] = ck[2];
+            plane_sums(sp, 2);  // cc/cx/ck[0..2]: planes z-1, z, z+1
+        }
         if (own) {
             const size_t c = (size_t)z * plane + (size_t)y * m + x;
             if (is_dir<3>(x, y, z, m, L.dir)) {
                 eout[c] = G ? (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)] : T(0);
+            } else if (!SIG) {
+                const T uc = cc[1];
+                T faces = cx[1] + (cc[0] + cc[2]);
+                T sum = faces;
+                if (RAD) {
+                    const T edges = ck[1] + (cx[0] + cx[2]);
+                    const T corners = ck[0] + ck[2];
+                    sum = faces + T(0.5) * edges + T(1.0 / 3.0) * corners;
+                }
+                const T r = scale * (sum - Wc * uc) + a * uc - g[c];
+                eout[c] = uc + tD * r;
+                if (pres) {
+                    const unsigned long long b = dbits((double)r);
+                    rb = b > rb ? b : rb;
+                }
             } else {
                 const int slots[3] = {sm, sc, sp};
                 const T uc = su[sc][ty + 1][tx + 1];
-                const T sgc = SIG ? ss[sc][ty + 1][tx + 1] : T(1);
+                const T sgc = ss[sc][ty + 1][tx + 1];
                 T acc[3] = {T(0), T(0), T(0)}, ds[3] = {T(0), T(0), T(0)};
 #pragma unroll
                 for (int dz = -1; dz <= 1; ++dz) {
@@ -70,28 +116,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
                             if (cls == 0 || (!RAD && cls != 1)) continue;
                             const int s = slots[dz + 1];
                             const T du = su[s][ty + 1 + dy][tx + 1 + dx] - uc;
-                            if (SIG) {
-                                const T t = ss[s][ty + 1 + dy][tx + 1 + dx] + sgc;
-                                acc[cls - 1] += t * du;
-                                ds[cls - 1] += t;
-                            } else {
-                                acc[cls - 1] += du;
-                            }
+                            const T t = ss[s][ty + 1 + dy][tx + 1 + dx] + sgc;
+                            acc[cls - 1] += t * du;
+                            ds[cls - 1] += t;
                         }
                     }
                 }
                 const T third = T(1.0 / 3.0);
                 const T sw = acc[0] + T(0.5) * acc[1] + third * acc[2];
-                T Lu, D;
-                if (SIG) {
-                    Lu = scale * T(0.5) * sw + a * uc;
-                    D = scale * T(0.5) * (ds[0] + T(0.5) * ds[1] + third * ds[2]) - a;
-                } else {
-                    Lu = scale * sw + a * uc;
-                    D = scale * (RAD ? T(6) + T(0.5) * T(12) + third * T(8) : T(6)) - a;
-                }
+                const T Lu = scale * T(0.5) * sw + a * uc;
+                const T D = scale * T(0.5) * (ds[0] + T(0.5) * ds[1] + third * ds[2]) - a;
                 const T r = Lu - g[c];
-                eout[c] = uc + (theta / D) * r;
+                eout[c] = uc + step_of3(theta, D) * r;
                 if (pres) {
                     const unsigned long long b = dbits((double)r);
                     rb = b > rb ? b : rb;

@@ -17,12 +17,13 @@
 // Wavefronts are independent: no LDS, no barriers.
 #include "sgml_device.h"
 
+#include <type_traits>
+
 namespace sgml {
 
 namespace {
 
 constexpr int kVisitBlock = 256;  // four independent wavefronts
-constexpr int kChunkRows = 128;
 
 // Element idx of a level array through a 32-bit byte offset (2D levels are
 // below 4 GiB): a scalar base plus one per-lane register, no 64-bit address
@@ -186,9 +187,9 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     // wavefront index, known to be uniform: row and strip arithmetic stays scalar
     const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sx = wid % strips, sy = wid / strips;
-    const int y0 = sy * kChunkRows;
+    const int y0 = sy * A.chunk;
     if (y0 >= m) return;  // the whole wavefront: past the last chunk
-    const int y1 = min(m, y0 + kChunkRows);
+    const int y1 = min(m, y0 + A.chunk);
     const int x = sx * W - HX + lane;
     const int xm = mir(x, m);
     const bool xout = lane >= HX && lane < HX + W && x < m;
@@ -227,15 +228,20 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     for (int k = 0; k < S + 2; ++k) sh[k] = T(1);
 
     const int rows = (y1 - y0) + 2 * S;
+    // bit k of ymask: input row - k lies on a Dirichlet y face (computed once
+    // per row, shifted along the pipeline)
+    unsigned ymask = 0;
     // one input row through the pipeline: the prolonged value enters
     // relaxation 1, each relaxation's output row enters the next one
-    auto step_row = [&](const RowIn<T> &R, int t) {
+    auto step_row = [&](const RowIn<T> &R, int t, auto hasg) {
+        constexpr bool HASG = decltype(hasg)::value;
         const int rho = y0 - S + t;  // input row, outside the grid: its image
         const int rm = mir(rho, m);
         T val = PRO ? prolonged<T>(R, xm, rm) : R.st;
 #pragma unroll
         for (int k = S; k > 0; --k) gh[k] = gh[k - 1];
         gh[0] = R.g;
+        ymask = (ymask << 1) | (unsigned)(((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1));
         if (SIG) {
 #pragma unroll
             for (int k = S + 1; k > 0; --k) sh[k] = sh[k - 1];
@@ -247,11 +253,9 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
             w[s][1] = w[s][2];
             w[s][2] = val;
             const int r = rho - s - 1;  // row relaxation s+1 produces now
-            const int rmr = mir(r, m);
-            const bool ydir = ((L.dir & 4u) && rmr == 0) || ((L.dir & 8u) && rmr == m - 1);
-            const bool dir = xdir || ydir;
+            const bool dir = xdir || ((ymask >> (s + 1)) & 1u);
             T gval = T(0);
-            if (G) gval = dir ? (T)ld(G, (unsigned)rmr * (unsigned)gpitch + (unsigned)glane) : T(0);
+            if (HASG && dir) gval = (T)ld(G, (unsigned)mir(r, m) * (unsigned)gpitch + (unsigned)glane);
             const T sg[3] = {sh[s + 2], sh[s + 1], sh[s]};
             T resid = T(0);
             val = relax<T, RAD, SIG, REC>(w[s], sg, gh[s + 1], dir, gval, K, resid);
@@ -276,17 +280,24 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
         for (int k = 0; k < B; ++k)
             if (t0 + k < rows) load_row<T, PRO, SIG>(q[k], A, xm, y0 - S + t0 + k, m);
     };
-    load_batch(qa, 0);
-    for (int t0 = 0; t0 < rows; t0 += 2 * B) {
-        load_batch(qb, t0 + B);
+    // the first cycle carries Dirichlet values: one copy of the row loop each
+    auto march = [&](auto hasg) {
+        load_batch(qa, 0);
+        for (int t0 = 0; t0 < rows; t0 += 2 * B) {
+            load_batch(qb, t0 + B);
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (t0 + k < rows) step_row(qa[k], t0 + k);
-        load_batch(qa, t0 + 2 * B);
+            for (int k = 0; k < B; ++k)
+                if (t0 + k < rows) step_row(qa[k], t0 + k, hasg);
+            load_batch(qa, t0 + 2 * B);
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (t0 + B + k < rows) step_row(qb[k], t0 + B + k);
-    }
+            for (int k = 0; k < B; ++k)
+                if (t0 + B + k < rows) step_row(qb[k], t0 + B + k, hasg);
+        }
+    };
+    if (G)
+        march(std::true_type());
+    else
+        march(std::false_type());
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         if (!REC || A.pres[s] < 0) continue;
@@ -319,9 +330,9 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     // wavefront index, known to be uniform: row and strip arithmetic stays scalar
     const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sx = wid % strips, sy = wid / strips;
-    const int y0 = sy * kChunkRows;
+    const int y0 = sy * A.chunk;
     if (y0 >= m) return;
-    const int y1 = min(m, y0 + kChunkRows);
+    const int y1 = min(m, y0 + A.chunk);
     const int x = sx * W - HX + lane;
     const int xm = mir(x, m);
     const bool xout = lane >= HX && lane < HX + W && x < m;
@@ -434,12 +445,22 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     if (lane == 0 && nb) atomicMax(A.norm + (size_t)(wid % kRedSlots) * kRedStride, nb);
 }
 
+// Rows per wavefront: short chunks give more wavefronts (the row chain of a
+// wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
+int chunk_rows(int requested, int m, int strips, int sweeps)
+{
+    if (requested > 0) return requested;
+    return (sweeps >= 4 && (long long)strips * m >= (1 << 18)) ? 32 : 16;
+}
+
 template <typename T, int RAD, int SIG, int S, int PRO, int REC>
-void launch_one(const VisitArgs &a, hipStream_t st)
+void launch_one(const VisitArgs &a0, hipStream_t st)
 {
     constexpr int W = 64 - 2 * (S + PRO);
+    VisitArgs a = a0;
     const int m = a.L.m;
-    const long long waves = (long long)((m + W - 1) / W) * ((m + kChunkRows - 1) / kChunkRows);
+    a.chunk = chunk_rows(a0.chunk, m, (m + W - 1) / W, S);
+    const long long waves = (long long)((m + W - 1) / W) * ((m + a.chunk - 1) / a.chunk);
     const unsigned blocks = (unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64));
     hipLaunchKernelGGL((k_visit2d<T, RAD, SIG, S, PRO, REC>), dim3(blocks), dim3(kVisitBlock), 0, st, a);
 }
@@ -475,10 +496,12 @@ void launch_rs(const VisitArgs &a, hipStream_t st)
 bool fused_visit_supported(int sweeps) { return sweeps == 1 || sweeps == 2 || sweeps == 4 || sweeps == 6; }
 
 template <typename T>
-void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
+void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st)
 {
+    CycleEndArgs a = a0;
     const int m = a.L.m;
-    const long long waves = (long long)((m + 61) / 62) * ((m + kChunkRows - 1) / kChunkRows);
+    a.chunk = a0.chunk > 0 ? a0.chunk : 32;
+    const long long waves = (long long)((m + 61) / 62) * ((m + a.chunk - 1) / a.chunk);
     const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
     if (v.radial && v.sigma)
         hipLaunchKernelGGL((k_cycle_end2d<T, 1, 1>), grid, block, 0, st, a);

@@ -17,6 +17,12 @@ import time
 
 import numpy as np
 
+# Kernel arguments in device memory rather than host-coherent memory: a cycle
+# issues some 45 small launches, each of which otherwise waits on a host
+# memory read for its arguments.  Read by the HIP runtime at initialisation,
+# so it is set before torch starts HIP.
+os.environ.setdefault("HIP_FORCE_DEV_KERNARG", "1")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -126,10 +132,16 @@ def main():
     for _ in range(args.warmup):
         plan.solve(f, G, u, tol=TOL, max_cycles=2000, precision=sgml.MIXED, stall_window=-1)
         plan.solve(f, G, u64, tol=TOL, max_cycles=2000, precision=sgml.FP64, stall_window=-1)
-    t_mix, st_mix = timed_solves(plan, f, G, u, sgml.MIXED, args.steps, True)
-    t_64, st_64 = timed_solves(plan, f, G, u64, sgml.FP64, args.steps, True)
-    print(f"# mixed: {t_mix * 1e3:.3f} ms/solve, {st_mix[-1]['cycles']} cycles; "
-          f"fp64: {t_64 * 1e3:.3f} ms/solve, {st_64[-1]['cycles']} cycles", file=sys.stderr, flush=True)
+    # the timed steps run uninstrumented; the same number of steps then runs
+    # again with HIP events around the level-0 launches (on the solve's
+    # stream) for the per-kernel durations of the roofline
+    t_mix, _ = timed_solves(plan, f, G, u, sgml.MIXED, args.steps, False)
+    t_64, _ = timed_solves(plan, f, G, u64, sgml.FP64, args.steps, False)
+    t_mix_p, st_mix = timed_solves(plan, f, G, u, sgml.MIXED, args.steps, True)
+    t_64_p, st_64 = timed_solves(plan, f, G, u64, sgml.FP64, args.steps, True)
+    print(f"# mixed: {t_mix * 1e3:.3f} ms/solve ({t_mix_p * 1e3:.3f} instrumented), {st_mix[-1]['cycles']} "
+          f"cycles; fp64: {t_64 * 1e3:.3f} ms/solve ({t_64_p * 1e3:.3f} instrumented), "
+          f"{st_64[-1]['cycles']} cycles", file=sys.stderr, flush=True)
 
     # accuracy of both results
     _, r_mix, norm0 = plan.residual(f, u, G=G)
@@ -140,13 +152,16 @@ def main():
     #   fused visit without injection (interpolation prologue + relaxations):
     #     read e (stale), source, coarse e (1/4 of the nodes); write e
     #   fused visit with injection: the same plus the coarse write (1/4)
-    #   cycle end: read e, u, s; write u, s, next source (FP64 u, s)
+    #   cycle end: read e, u, s; write u, s (FP64); mixed: write the next
+    #   source (FP32) and, in 2D, its restriction to level 1 (1/4 of the nodes)
     sm, s6 = st_mix[-1], st_64[-1]
 
     def kernel_rates(st, tb):
         out = {}
+        mixed = tb == 4
         per_node = {"visit0": 3 * tb + tb / 4, "visit0_inject": 3 * tb + tb / 2,
-                    "sweep0": 3 * tb, "cycle_end": tb + 8 * 4 + (4 if tb == 4 else 0)}
+                    "sweep0": 3 * tb,
+                    "cycle_end": tb + 8 * 4 + (4 if mixed else 0) + (tb / 4 if mixed and wl.dim == 2 else 0)}
         for name, rec in st["prof"].items():
             if rec["launches"] == 0:
                 continue
@@ -179,6 +194,7 @@ def main():
         "config": {"workload": f"{wl.name} {wl.N}^{wl.dim}", "nodes": wl.nodes,
                    "stencil": "radial" if wl.stencil else "axis", "faces": wl.faces,
                    "tol": TOL, "precision": "fp32 cycle + fp64 refinement", "n_r": 2},
+        "ms_per_step_instrumented": t_mix_p * 1e3,
         "fp64": {"value": wl.nodes / t_64 / 1e9, "ms_per_step": t_64 * 1e3,
                  "cycles": s6["cycles"], "relres_true": r_64 / norm0, "kernels": k_64},
         "mixed": {"cycles": sm["cycles"], "relres": sm["relres"], "relres_true": r_mix / norm0,

@@ -69,8 +69,8 @@ enum { SGML_AXIS = 0, SGML_RADIAL = 1 };
  *               solution stay FP64 (outer iterative refinement). */
 enum { SGML_FP64 = 0, SGML_MIXED = 1 };
 
-/* Visit order of Algorithm 3.  SGML_SCHEDULE_ONCE: lines 9-10 (the level-0
- * relaxations) run once after the loop over teeth; SGML_SCHEDULE_EACH: they
+/* Visit order of Algorithm 3.  SGML_SCHEDULE_ONCE: the closing level-0
+ * relaxations run once after the loop over teeth; SGML_SCHEDULE_EACH: they
  * run after every tooth. */
 enum { SGML_SCHEDULE_ONCE = 0, SGML_SCHEDULE_EACH = 1 };
 

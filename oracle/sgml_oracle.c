@@ -59,7 +59,7 @@ typedef struct {
     double tol;       /* stop when the recursive relative residual <= tol */
     int max_cycles;
     int n_r;          /* cap on relaxation-interpolations per visit, <= 0: none */
-    int reading;      /* 0: Algorithm 3 lines 9-10 run once after the loop; 1: inside it */
+    int reading;      /* 0: the closing level-0 relaxations of Algorithm 3 run once after the loop; 1: inside it */
     int stall_window; /* STAGNATED when the residual has not halved over this many
                          cycles; 0: 3, < 0: never */
 } orc_opts;
@@ -346,9 +346,9 @@ static double relax_interp(const grid_t *g, int nu, const double *u1, double *u,
 
 /* Algorithm 3 as a list of visits (level, number of relaxation-interpolations).
  * Tooth nu1 = n-1 .. 0 visits nu1, nu1-1 (skipped when negative) and nu1,
- * each min(n_r, 2^(n-nu1)) times.  Reading 0: lines 9-10 (level 0,
- * min(n_r, 2^n) times) run once after the loop; reading 1: at the end of
- * every tooth.  n_r <= 0 means full doubling (Fig. 1). */
+ * each min(n_r, 2^(n-nu1)) times.  Reading 0: the closing level-0
+ * relaxations (min(n_r, 2^n) times) run once after the loop; reading 1: at
+ * the end of every tooth.  n_r <= 0 means full doubling (Fig. 1). */
 int orc_schedule(int n, int n_r, int reading, int *level, int *count, int cap)
 {
     int len = 0;

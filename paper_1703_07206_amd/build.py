@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsgml.so")
-SOURCES = ["sgml_kernels.hip", "sgml_visit2d.hip", "sgml_sweep3d.hip", "sgml_plan.hip"]
+SOURCES = ["sgml_kernels.hip", "sgml_visit2d.hip", "sgml_tile2d.hip", "sgml_sweep3d.hip", "sgml_plan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

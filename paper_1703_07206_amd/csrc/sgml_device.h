@@ -5,10 +5,15 @@
 
 namespace sgml {
 
-__device__ __forceinline__ size_t lin(int i, int j, int k, int m)
+// Linear index of node (i, j, k) of an m^d array, in index type I (int where
+// the array is known to be small, as in LDS).
+template <typename I>
+__device__ __forceinline__ I lin_as(int i, int j, int k, int m)
 {
-    return ((size_t)k * (size_t)m + (size_t)j) * (size_t)m + (size_t)i;
+    return ((I)k * (I)m + (I)j) * (I)m + (I)i;
 }
+
+__device__ __forceinline__ size_t lin(int i, int j, int k, int m) { return lin_as<size_t>(i, j, k, m); }
 
 // Image of a coordinate across a face (node reflection).  For unknown nodes
 // it only triggers at Neumann faces: an unknown is never on a Dirichlet face.
@@ -18,12 +23,14 @@ __device__ __forceinline__ int mir(int c, int m)
     return c > m - 1 ? 2 * (m - 1) - c : c;
 }
 
+// Whether node (i, j, k) lies on a Dirichlet face (bit f of dir: face f of
+// x-, x+, y-, y+, z-, z+).  Bitwise, so that it compiles without branches.
 template <int DIM>
 __device__ __forceinline__ bool is_dir(int i, int j, int k, int m, unsigned dir)
 {
-    bool d = ((dir & 1u) && i == 0) || ((dir & 2u) && i == m - 1) || ((dir & 4u) && j == 0) ||
-             ((dir & 8u) && j == m - 1);
-    if (DIM == 3) d = d || ((dir & 16u) && k == 0) || ((dir & 32u) && k == m - 1);
+    bool d = (((dir & 1u) != 0) & (i == 0)) | (((dir & 2u) != 0) & (i == m - 1)) |
+             (((dir & 4u) != 0) & (j == 0)) | (((dir & 8u) != 0) & (j == m - 1));
+    if (DIM == 3) d = d | (((dir & 16u) != 0) & (k == 0)) | (((dir & 32u) != 0) & (k == m - 1));
     return d;
 }
 

@@ -55,6 +55,31 @@ struct CoarseOp {
 // 27-point stencil needs more than the 128 registers a 16-wave group allows
 constexpr int coarse_threads(int dim) { return dim == 3 ? 512 : 1024; }
 
+// The same run with its level arrays staged in LDS (k_coarse_lds): operands
+// are element offsets into the workgroup's LDS; the coefficient and the
+// Dirichlet values stay in global memory.  The largest level a run may touch
+// has coarse_lds_nodes() nodes (a fixed number per thread).
+constexpr int coarse_lds_nodes(int dim) { return dim == 3 ? 5120 : 5120; }
+struct LdsOp {
+    int kind;         // kOp*
+    int m;            // nodes per axis of the level written
+    int first;        // prolongation: the finer level's stale values are zero
+    int target;       // sweeps: reduction target of the pseudo-residual, -1 for none
+    int in0, in1;     // element offsets of the operands (as CoarseOp::in0 / in1)
+    int out;          // element offset of the result
+    int nodes;        // m^d
+    float inv_m;      // 1 / m in float
+    int pad;
+    const void *sig;  // sweeps: level coefficient (global memory) or null
+    Level L;          // sweeps: constants of the level
+};
+// A copy between global memory and the LDS image before (loads) or after
+// (stores) the run.
+struct LdsXfer {
+    void *ptr;
+    int off, count;   // LDS element offset, elements
+};
+
 // A fused visit of a 2D level: optional interpolation of the next coarser
 // level's pending variation (prologue), `sweeps` relaxations, optional
 // injection of the result into the next coarser level (epilogue).
@@ -84,9 +109,11 @@ struct CycleEndArgs {
     const double *G;      // Dirichlet values (first cycle) or null
     const double *sigma;  // coefficient (FP64, full grid) or null
     double *u, *s;        // collected solution and recursive residual
+    double *s_out;        // the new residual, when not written in place (RES: s is read at halo nodes)
     void *shat;           // next cycle's source in the cycle's precision (mixed) or null
     double shat_scale;
     unsigned long long *norm;  // reduction target of max |s|
+    void *g1;             // 2D: next cycle's level-1 source (restriction of the new source) or null
     Level L;
     int chunk;            // rows per wavefront (2D)
 };
@@ -103,8 +130,20 @@ template <typename T>
 void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level *levels, const double *G,
                    unsigned long long *targets, hipStream_t st);
 
+// `lds_bytes` covers the level arrays and, from byte ops_off on, the nops
+// operations.  Returns false when the launch cannot get that much LDS.
+template <typename T>
+bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload,
+                       int nstore, size_t lds_bytes, const double *G, unsigned long long *targets, hipStream_t st);
+
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
+
+// The same visit on a 2D level, tile by tile in LDS, for the levels coarser
+// than 0 that tile_visit_supported accepts.
+bool tile_visit_supported(int m);
+template <typename T>
+void launch_visit_tile(const Variant &v, const VisitArgs &a, hipStream_t st);
 
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st);

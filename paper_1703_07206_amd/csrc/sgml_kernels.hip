@@ -58,11 +58,11 @@ __device__ __forceinline__ void block_max(unsigned long long v, unsigned long lo
 // w = 1 for face neighbours, 1/2 for edge and 1/3 for corner neighbours
 // (radial), scale = C/(lam h)^2 with C = 1 (axis) or 2d/(3^d - 1) (radial).
 // Differences are taken before summing, per neighbour class.
-template <typename T, int DIM, int RAD, int SIG>
+template <typename T, int DIM, int RAD, int SIG, typename I = size_t>
 __device__ __forceinline__ void stencil(const T *__restrict__ u, const T *__restrict__ sig, int i,
                                         int j, int k, int m, T scale, T a, T &Lu, T &D)
 {
-    const size_t c = lin(i, j, k, m);
+    const I c = lin_as<I>(i, j, k, m);
     const T uc = u[c];
     const T sc = SIG ? sig[c] : T(1);
     T acc[3] = {T(0), T(0), T(0)};
@@ -77,7 +77,7 @@ __device__ __forceinline__ void stencil(const T *__restrict__ u, const T *__rest
             for (int dx = -1; dx <= 1; ++dx) {
                 const int cls = (dx != 0) + (dy != 0) + (dz != 0);
                 if (cls == 0 || (!RAD && cls != 1)) continue;
-                const size_t q = lin(mir(i + dx, m), jj, kk, m);
+                const I q = lin_as<I>(mir(i + dx, m), jj, kk, m);
                 const T du = u[q] - uc;
                 if (SIG) {
                     const T t = sig[q] + sc;
@@ -163,26 +163,73 @@ __global__ void k_fill(T *p, size_t count, T value)
     for (; t < count; t += stride) p[t] = value;
 }
 
-// One relaxation (forward-Euler step of eq. (2), Algorithm 2 lines 3-4) of
-// one node of a level, Jacobi style: reads ein, writes eout.  Unknowns:
-// e += theta/D (dL e - g).  Dirichlet nodes take the prescribed value G (the
-// variation G - e of Sec. 2) or 0.  Returns the bits of |dL e - g|.
+// One relaxation (forward-Euler step of eq. (2), Algorithm 2) of one node of
+// a level, Jacobi style: the new value from ein.  Unknowns:
+// e + theta/D (dL e - g).  Dirichlet nodes take the prescribed value G (the
+// variation G - e of Sec. 2) or 0.  rb: the bits of |dL e - g| (0 at
+// Dirichlet nodes).
+template <typename T, int DIM, int RAD, int SIG, typename I = size_t>
+__device__ __forceinline__ T sweep_value(const T *__restrict__ ein, const T *__restrict__ g,
+                                         const T *__restrict__ sig, const double *__restrict__ G,
+                                         const Level &L, int i, int j, int k, unsigned long long &rb)
+{
+    const I c = lin_as<I>(i, j, k, L.m);
+    if (is_dir<DIM>(i, j, k, L.m, L.dir)) {
+        rb = 0;
+        return G ? (T)G[lin(i * L.lam, j * L.lam, k * L.lam, L.N)] : T(0);
+    }
+    T Lu, D;
+    stencil<T, DIM, RAD, SIG, I>(ein, sig, i, j, k, L.m, (T)L.scale, (T)L.a, Lu, D);
+    const T r = Lu - g[c];
+    rb = dbits((double)r);
+    return ein[c] + ((T)L.theta / D) * r;
+}
+
+// sweep_value for a level held in LDS: 32-bit indices, the level constants
+// already in T, theta/D precomputed when sigma = 1 (D is then the same at
+// every node), and the residual bits only when they are recorded.
+template <typename T>
+struct SweepConst {
+    T scale, a, theta, step;  // step = theta / D (sigma = 1)
+};
+
+template <typename T, int DIM, int RAD, int SIG>
+__device__ __forceinline__ T lds_sweep_value(const T *__restrict__ ein, const T *__restrict__ g,
+                                             const T *__restrict__ sig, const double *__restrict__ G,
+                                             const Level &L, const SweepConst<T> &K, int i, int j, int k,
+                                             bool want_rb, unsigned long long &rb)
+{
+    const int c = lin_as<int>(i, j, k, L.m);
+    if (is_dir<DIM>(i, j, k, L.m, L.dir)) return G ? (T)G[lin(i * L.lam, j * L.lam, k * L.lam, L.N)] : T(0);
+    T Lu, D;
+    stencil<T, DIM, RAD, SIG, int>(ein, sig, i, j, k, L.m, K.scale, K.a, Lu, D);
+    const T r = Lu - g[c];
+    if (want_rb) {
+        const unsigned long long b = dbits((double)r);
+        rb = b > rb ? b : rb;
+    }
+    return ein[c] + (SIG ? K.theta / D : K.step) * r;
+}
+
+// The diagonal D of the operator when sigma = 1 (see stencil).
+template <typename T, int DIM, int RAD>
+__device__ __forceinline__ T const_diag(T scale, T a)
+{
+    constexpr int n2 = RAD ? (DIM == 3 ? 12 : 4) : 0;
+    constexpr int n3 = (RAD && DIM == 3) ? 8 : 0;
+    const T W = T(2 * DIM) + T(0.5) * T(n2) + T(1.0 / 3.0) * T(n3);
+    return scale * W - a;
+}
+
 template <typename T, int DIM, int RAD, int SIG>
 __device__ __forceinline__ unsigned long long sweep_node(const T *__restrict__ ein, T *__restrict__ eout,
                                                          const T *__restrict__ g, const T *__restrict__ sig,
                                                          const double *__restrict__ G, const Level &L,
                                                          int i, int j, int k)
 {
-    const size_t c = lin(i, j, k, L.m);
-    if (is_dir<DIM>(i, j, k, L.m, L.dir)) {
-        eout[c] = G ? (T)G[lin(i * L.lam, j * L.lam, k * L.lam, L.N)] : T(0);
-        return 0;
-    }
-    T Lu, D;
-    stencil<T, DIM, RAD, SIG>(ein, sig, i, j, k, L.m, (T)L.scale, (T)L.a, Lu, D);
-    const T r = Lu - g[c];
-    eout[c] = ein[c] + ((T)L.theta / D) * r;
-    return dbits((double)r);
+    unsigned long long rb;
+    eout[lin(i, j, k, L.m)] = sweep_value<T, DIM, RAD, SIG>(ein, g, sig, G, L, i, j, k, rb);
+    return rb;
 }
 
 // Interpolation of the pending variation of level nu (compact, mc nodes per
@@ -191,18 +238,14 @@ __device__ __forceinline__ unsigned long long sweep_node(const T *__restrict__ e
 // first visit of a cycle); coarse nodes take ec directly, the others add the
 // multilinear (tensor hat) interpolation -- the mean of the 2, 4 or 8
 // enclosing coarse nodes.
-template <typename T, int DIM>
-__device__ __forceinline__ void prolong_node(const T *__restrict__ ec, const T *__restrict__ efin,
-                                             T *__restrict__ efout, int mc, int first, int i, int j, int k)
+template <typename T, int DIM, typename I = size_t>
+__device__ __forceinline__ T prolong_value(const T *__restrict__ ec, const T *__restrict__ efin, int mc,
+                                           int first, int i, int j, int k)
 {
     const int mf = 2 * mc - 1;
     const int ci = i >> 1, cj = j >> 1, ck = k >> 1;
     const int oi = i & 1, oj = j & 1, ok = DIM == 3 ? (k & 1) : 0;
-    const size_t f = lin(i, j, k, mf);
-    if (!(oi | oj | ok)) {
-        efout[f] = ec[lin(ci, cj, ck, mc)];
-        return;
-    }
+    if (!(oi | oj | ok)) return ec[lin_as<I>(ci, cj, ck, mc)];
     T acc = T(0);
 #pragma unroll
     for (int c = 0; c <= (DIM == 3 ? 1 : 0); ++c) {
@@ -214,14 +257,21 @@ __device__ __forceinline__ void prolong_node(const T *__restrict__ ec, const T *
             for (int a = 0; a <= 1; ++a) {
                 if (a && !oi) continue;
                 const int X = ci + a, Y = cj + b, Z = ck + c;
-                T p = ec[lin(X, Y, Z, mc)];
-                if (!first) p -= efin[lin(2 * X, 2 * Y, 2 * Z, mf)];
+                T p = ec[lin_as<I>(X, Y, Z, mc)];
+                if (!first) p -= efin[lin_as<I>(2 * X, 2 * Y, 2 * Z, mf)];
                 acc += p;
             }
         }
     }
     const T w = T(1) / T(1 << (oi + oj + ok));
-    efout[f] = (first ? T(0) : efin[f]) + w * acc;
+    return (first ? T(0) : efin[lin_as<I>(i, j, k, mf)]) + w * acc;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void prolong_node(const T *__restrict__ ec, const T *__restrict__ efin,
+                                             T *__restrict__ efout, int mc, int first, int i, int j, int k)
+{
+    efout[lin(i, j, k, 2 * mc - 1)] = prolong_value<T, DIM>(ec, efin, mc, first, i, j, k);
 }
 
 // Values of level nu-1 at the level-nu nodes (the schedule climbs a level).
@@ -236,9 +286,8 @@ __device__ __forceinline__ void inject_node(const T *__restrict__ ef, T *__restr
 // fine level's 3^d neighbours of 2X with weights hat(p/2) per axis over 2^d;
 // samples outside the grid are images.  Summed in the same order (z, y, x
 // outer to inner) with exactly representable weights.
-template <typename Tin, typename Tout, int DIM>
-__device__ __forceinline__ void restrict_node(const Tin *__restrict__ fine, Tout *__restrict__ coarse, int mc,
-                                              int i, int j, int k)
+template <typename Tin, typename Tout, int DIM, typename I = size_t>
+__device__ __forceinline__ Tout restrict_value(const Tin *__restrict__ fine, int mc, int i, int j, int k)
 {
     using Acc = typename std::conditional<sizeof(Tin) == 8 || sizeof(Tout) == 8, double, float>::type;
     const int mf = 2 * mc - 1;
@@ -254,11 +303,18 @@ __device__ __forceinline__ void restrict_node(const Tin *__restrict__ fine, Tout
 #pragma unroll
             for (int p = -1; p <= 1; ++p) {
                 const Acc wp = p == 0 ? Acc(1) : Acc(0.5);
-                acc += (wp * wq * wr) * (Acc)fine[lin(mir(2 * i + p, mf), jj, kk, mf)];
+                acc += (wp * wq * wr) * (Acc)fine[lin_as<I>(mir(2 * i + p, mf), jj, kk, mf)];
             }
         }
     }
-    coarse[lin(i, j, k, mc)] = (Tout)(acc / Acc(1 << DIM));
+    return (Tout)(acc / Acc(1 << DIM));
+}
+
+template <typename Tin, typename Tout, int DIM>
+__device__ __forceinline__ void restrict_node(const Tin *__restrict__ fine, Tout *__restrict__ coarse, int mc,
+                                              int i, int j, int k)
+{
+    coarse[lin(i, j, k, mc)] = restrict_value<Tin, Tout, DIM>(fine, mc, i, j, k);
 }
 
 template <typename T, int DIM, int RAD, int SIG>
@@ -343,6 +399,137 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse(const CoarseOp *
         }
         if (op.kind == kOpSweep && op.target >= 0) block_max(rb, targets + (size_t)op.target * kRedWords);
         __syncthreads();
+    }
+}
+
+// The coarse run of k_coarse with its level arrays in LDS: the arrays the run
+// reads before writing are copied in, every operation works LDS to LDS (one
+// barrier each), and the arrays read after the run are copied back.  The
+// operation list is copied in too (at ops_off bytes), so that no operation
+// waits on a global load.  Thread
+// t owns nodes t, t + threads, ... of the level an operation writes; it
+// computes all of them before storing any, so the loads of a thread issue
+// together.  Each operation reads one buffer of a level and writes the other
+// (or another level), as in k_coarse.
+template <typename T, int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp *__restrict__ ops, int nops,
+                                                               int ops_off, const LdsXfer *__restrict__ xfer,
+                                                               int nload, int nstore,
+                                                               const double *__restrict__ G,
+                                                               unsigned long long *__restrict__ targets)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *sm = reinterpret_cast<T *>(lds_raw);
+    LdsOp *sops = reinterpret_cast<LdsOp *>(lds_raw + ops_off);
+    constexpr int NT = coarse_threads(DIM);
+    constexpr int KMAX = coarse_lds_nodes(DIM) / NT;
+    static_assert(sizeof(LdsOp) % 4 == 0, "LdsOp is copied as words");
+    const int tid = threadIdx.x;
+    {
+        const unsigned *src = reinterpret_cast<const unsigned *>(ops);
+        unsigned *dst = reinterpret_cast<unsigned *>(sops);
+        const int words = nops * (int)(sizeof(LdsOp) / 4);
+        for (int t = tid; t < words; t += NT) dst[t] = src[t];
+    }
+    for (int x = 0; x < nload; ++x) {
+        const T *src = static_cast<const T *>(xfer[x].ptr);
+        const int off = xfer[x].off, count = xfer[x].count;
+#pragma unroll 4
+        for (int t = tid; t < count; t += NT) sm[off + t] = src[t];
+    }
+    __syncthreads();
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // first node of this wave
+    for (int o = 0; o < nops; ++o) {
+        const LdsOp &op = sops[o];
+        // uniform over the workgroup: the fields the control flow uses go to scalars
+        const int kind = __builtin_amdgcn_readfirstlane(op.kind);
+        const int m = __builtin_amdgcn_readfirstlane(op.m);
+        const int nodes = __builtin_amdgcn_readfirstlane(op.nodes);
+        const int target = __builtin_amdgcn_readfirstlane(op.target);
+        unsigned long long rb = 0;
+        if (wbase < nodes) {  // waves past the level's last node only meet the barrier
+            const float inv = op.inv_m;
+            const int in0 = __builtin_amdgcn_readfirstlane(op.in0);
+            const int in1 = __builtin_amdgcn_readfirstlane(op.in1);
+            const int first = __builtin_amdgcn_readfirstlane(op.first);
+            // node t = (k m + j) m + i; (t + 1/2) / m is at least 1/(2m) away
+            // from an integer, far beyond the float error for t < 2^13
+            auto decode = [&](int t, int &i, int &j, int &k) {
+                const int q = (int)(((float)t + 0.5f) * inv);
+                i = t - q * m;
+                if (DIM == 3) {
+                    k = (int)(((float)q + 0.5f) * inv);
+                    j = q - k * m;
+                } else {
+                    j = q;
+                    k = 0;
+                }
+            };
+            T val[KMAX];
+            // f(t, i, j, k) -> value of node t, for the nodes of this thread
+            auto each = [&](auto f) {
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q) {
+                    const int t = tid + q * NT;
+                    if (wbase + q * NT < nodes && t < nodes) {
+                        int i, j, k;
+                        decode(t, i, j, k);
+                        val[q] = f(t, i, j, k);
+                    }
+                }
+            };
+            switch (kind) {
+            case kOpSweep: {
+                const T *ein = sm + in0, *g = sm + in1;
+                const T *sig = static_cast<const T *>(op.sig);
+                const Level L = op.L;
+                SweepConst<T> K;
+                K.scale = (T)L.scale;
+                K.a = (T)L.a;
+                K.theta = (T)L.theta;
+                K.step = K.theta / const_diag<T, DIM, RAD>(K.scale, K.a);
+                const bool want_rb = target >= 0;
+                each([&](int, int i, int j, int k) {
+                    return lds_sweep_value<T, DIM, RAD, SIG>(ein, g, sig, G, L, K, i, j, k, want_rb, rb);
+                });
+                break;
+            }
+            case kOpProlong: {
+                const T *ec = sm + in0, *efin = sm + in1;
+                const int mc = (m + 1) / 2;
+                each([&](int, int i, int j, int k) { return prolong_value<T, DIM, int>(ec, efin, mc, first, i, j, k); });
+                break;
+            }
+            case kOpInject: {
+                const T *ef = sm + in0;
+                const int mf = 2 * m - 1;
+                each([&](int, int i, int j, int k) { return ef[lin_as<int>(2 * i, 2 * j, 2 * k, mf)]; });
+                break;
+            }
+            case kOpRestrict: {
+                const T *fine = sm + in0;
+                each([&](int, int i, int j, int k) { return restrict_value<T, T, DIM, int>(fine, m, i, j, k); });
+                break;
+            }
+            default:  // kOpFill
+                each([&](int, int, int, int) { return T(0); });
+                break;
+            }
+            T *out = sm + __builtin_amdgcn_readfirstlane(op.out);
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q) {
+                const int t = tid + q * NT;
+                if (wbase + q * NT < nodes && t < nodes) out[t] = val[q];
+            }
+        }
+        if (kind == kOpSweep && target >= 0) block_max(rb, targets + (size_t)target * kRedWords);
+        __syncthreads();
+    }
+    for (int x = nload; x < nload + nstore; ++x) {
+        T *dst = static_cast<T *>(xfer[x].ptr);
+        const int off = xfer[x].off, count = xfer[x].count;
+#pragma unroll 4
+        for (int t = tid; t < count; t += NT) dst[t] = sm[off + t];
     }
 }
 
@@ -521,6 +708,17 @@ void dispatch3(const Variant &v, A &&...args)
 #undef SGML_CASE
 }
 
+template <typename R, template <int, int, int> class K, typename... A>
+R dispatch3r(const Variant &v, A &&...args)
+{
+#define SGML_CASE(D, RA, S) \
+    if (v.dim == D && v.radial == RA && v.sigma == S) return K<D, RA, S>::run(std::forward<A>(args)...);
+    SGML_CASE(2, 0, 0) SGML_CASE(2, 0, 1) SGML_CASE(2, 1, 0) SGML_CASE(2, 1, 1)
+    SGML_CASE(3, 0, 0) SGML_CASE(3, 0, 1) SGML_CASE(3, 1, 0) SGML_CASE(3, 1, 1)
+#undef SGML_CASE
+    return R();
+}
+
 dim3 block_of() { return dim3(BX, BY, 1); }
 
 }  // namespace
@@ -577,6 +775,39 @@ void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level 
                    unsigned long long *targets, hipStream_t st)
 {
     dispatch3<CoarseRun<T>::template K>(v, ops, nops, levels, G, targets, st);
+}
+
+namespace {
+template <typename T>
+struct CoarseLdsRun {
+    template <int D, int R, int S>
+    struct K {
+        static bool run(const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload, int nstore,
+                        size_t bytes, const double *G, unsigned long long *targets, hipStream_t st)
+        {
+            static size_t granted = 0;  // dynamic LDS this instantiation may use
+            if (bytes > granted) {
+                if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_lds<T, D, R, S>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return false;
+                }
+                granted = bytes;
+            }
+            hipLaunchKernelGGL((k_coarse_lds<T, D, R, S>), dim3(1), dim3(coarse_threads(D)), bytes, st, ops,
+                               nops, ops_off, xfer, nload, nstore, G, targets);
+            return true;
+        }
+    };
+};
+}  // namespace
+
+template <typename T>
+bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload,
+                       int nstore, size_t lds_bytes, const double *G, unsigned long long *targets, hipStream_t st)
+{
+    return dispatch3r<bool, CoarseLdsRun<T>::template K>(v, ops, nops, ops_off, xfer, nload, nstore, lds_bytes, G,
+                                                         targets, st);
 }
 
 template <typename T>
@@ -715,6 +946,10 @@ template void launch_coarse<double>(const Variant &, const CoarseOp *, int, cons
                                     unsigned long long *, hipStream_t);
 template void launch_coarse<float>(const Variant &, const CoarseOp *, int, const Level *, const double *,
                                    unsigned long long *, hipStream_t);
+template bool launch_coarse_lds<double>(const Variant &, const LdsOp *, int, int, const LdsXfer *, int, int,
+                                        size_t, const double *, unsigned long long *, hipStream_t);
+template bool launch_coarse_lds<float>(const Variant &, const LdsOp *, int, int, const LdsXfer *, int, int,
+                                       size_t, const double *, unsigned long long *, hipStream_t);
 template void launch_prolong<double>(int, int, const double *, const double *, double *, bool, hipStream_t);
 template void launch_prolong<float>(int, int, const float *, const float *, float *, bool, hipStream_t);
 template void launch_inject<double>(int, int, const double *, double *, hipStream_t);

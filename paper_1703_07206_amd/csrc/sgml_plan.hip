@@ -25,11 +25,12 @@ constexpr size_t kScalars = (size_t)kTargets * kRedWords;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kMaxCoarseOps = 4096;
+constexpr int kMaxXfers = 2048;
 constexpr int kDefaultCoarseNodes = 5000;
-constexpr int kDefaultFuseMin = 1025;  // smallest 2D level (nodes per axis) visited in one fused pass
+constexpr int kDefaultFuseMin = 129;  // smallest 2D level (nodes per axis) visited in one fused pass
 
 struct Layout {
-    size_t scal, ops, levels, s, e0, shat, sig0t;
+    size_t scal, ops, lops, xfer, levels, s, s2, e0, shat, sig0t;
     size_t e[kMaxLevels][2], g[kMaxLevels], sig64[kMaxLevels], sigt[kMaxLevels];
     size_t total;
 };
@@ -70,10 +71,13 @@ Layout make_layout(const sgml_problem *p, int precision)
     };
     L.scal = take(sizeof(unsigned long long) * kScalars);
     L.ops = take(sizeof(CoarseOp) * kMaxCoarseOps);
+    L.lops = take(sizeof(LdsOp) * kMaxCoarseOps);
+    L.xfer = take(sizeof(LdsXfer) * kMaxXfers);
     L.levels = take(sizeof(Level) * kMaxLevels);
     L.s = take(8 * M);
     L.e0 = take(2 * 8 * M);  // two level-0 buffers, FP64-sized (FP32 uses half)
     L.shat = mixed ? take(4 * M) : 0;
+    L.s2 = mixed ? take(8 * M) : 0;  // second residual buffer (2D mixed cycle end)
     L.sig0t = mixed ? take(4 * M) : 0;
     for (int nu = 1; nu < p->n; ++nu) {
         const size_t c = level_nodes(p->dim, p->n, nu);
@@ -89,8 +93,8 @@ Layout make_layout(const sgml_problem *p, int precision)
 
 // Algorithm 3 as a visit list.  Tooth nu1 = n-1 .. 0 visits nu1, nu1 - 1
 // (not below 0) and nu1 again, each min(n_r, 2^(n - nu1)) times; the
-// level-0 relaxations of lines 9-10 (min(n_r, 2^n) times) close the cycle
-// once (SGML_SCHEDULE_ONCE) or every tooth (SGML_SCHEDULE_EACH).
+// algorithm's closing level-0 relaxations (min(n_r, 2^n) times) end the
+// cycle once (SGML_SCHEDULE_ONCE) or every tooth (SGML_SCHEDULE_EACH).
 void build_schedule(int n, int n_r, int sched, std::vector<int> &lev, std::vector<int> &cnt)
 {
     lev.clear();
@@ -121,6 +125,15 @@ double default_theta(int dim, int stencil)
     return dim == 2 ? 0.8 : 6.0 / 7.0;
 }
 
+// A run of consecutive coarse operations, launched as one workgroup.
+struct RunDesc {
+    int op0, nops;             // range of the device CoarseOp list (k_coarse)
+    int lds;                   // staged in LDS (k_coarse_lds)
+    int lop0, x0, nload, nstore;
+    int ops_off;               // LDS byte offset of the staged operation list
+    size_t lds_bytes;
+};
+
 }  // namespace
 
 struct sgml_plan {
@@ -141,7 +154,11 @@ struct sgml_plan {
     std::vector<hipEvent_t> pev;  // profiling events, pairs around timed launches
     size_t pev_used = 0;
     CoarseOp *ops_host;           // pinned staging of the coarse operation list
+    LdsOp *lops_host;             // ... and of its LDS form
+    LdsXfer *xfer_host;
     Level *levels_host;           // pinned staging of the level table
+    size_t lds_max;               // LDS bytes one workgroup may allocate
+    std::vector<RunDesc> runs;        // the coarse runs of the compiled cycle, in order
 
     template <typename T>
     T *at(size_t off) const
@@ -209,7 +226,8 @@ hipEvent_t *prof_pair(sgml_plan *P)
     if (P->pev_used + 2 > P->pev.size()) {
         for (int t = 0; t < 64; ++t) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // timing only: no system-scope fence (no cache writeback) at each record
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             P->pev.push_back(e);
         }
     }
@@ -246,7 +264,7 @@ struct HostOp {
 // the cycle's e at the end.
 template <typename T>
 const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev, const std::vector<int> &cnt,
-                       bool record, int coarse_level, int fuse_min, std::vector<HostOp> &ops,
+                       bool record, int coarse_level, int fuse_min, bool restrict1_outside, std::vector<HostOp> &ops,
                        long long &updates_per_cycle)
 {
     const int n = P->n;
@@ -288,8 +306,10 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
         sig[nu] = P->var.sigma ? (mixed ? (const T *)P->at<T>(P->lay.sigt[nu])
                                         : (const T *)P->at<T>(P->lay.sig64[nu]))
                                : nullptr;
-        // restriction(nu) of the cycle source (Algorithm 1), kept for the cycle
-        push(kOpRestrict, nu, 0, -1, g[nu - 1], nullptr, nullptr, gn, nu - 1 >= coarse_level);
+        // restriction(nu) of the cycle source (Algorithm 1), kept for the cycle;
+        // the first step may come with the source (restrict1_outside)
+        if (nu > 1 || !restrict1_outside)
+            push(kOpRestrict, nu, 0, -1, g[nu - 1], nullptr, nullptr, gn, nu - 1 >= coarse_level);
     }
     int cur[kMaxLevels] = {0};
     bool seen[kMaxLevels] = {false};
@@ -394,10 +414,152 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
     return E[0][cur[0]];
 }
 
-// Upload the coarse operations (in execution order) and the level table; the
-// device copy serves every cycle of the solve.  Coarse runs beyond the
-// buffer's capacity fall back to separate launches.
-sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, hipStream_t st)
+// Buffers an operation reads and writes (reads listed first), with their
+// lengths.  Level coefficients are not listed: they stay in global memory.
+struct Ref {
+    const void *p;
+    size_t count;
+    bool write;
+};
+
+int op_refs(const sgml_plan *P, const HostOp &h, Ref r[6])
+{
+    const CoarseOp &o = h.op;
+    int k = 0;
+    auto ref = [&](const void *p, int nu, bool w) {
+        if (p) r[k++] = {p, level_nodes(P->dim, P->n, nu), w};
+    };
+    switch (o.kind) {
+    case kOpFill:
+        ref(o.out, o.level, true);
+        break;
+    case kOpSweep:
+        ref(o.in0, o.level, false);
+        ref(o.in1, o.level, false);
+        ref(o.out, o.level, true);
+        break;
+    case kOpProlong:
+        ref(o.in0, o.level + 1, false);
+        if (!o.first) ref(o.in1, o.level, false);
+        ref(o.out, o.level, true);
+        break;
+    case kOpInject:
+    case kOpRestrict:
+        ref(o.in0, o.level - 1, false);
+        ref(o.out, o.level, true);
+        break;
+    case kOpVisit: {
+        const VisitArgs &a = h.visit;
+        ref(a.estale, o.level, false);
+        if (a.prolong) ref(a.ecoarse, o.level + 1, false);
+        ref(a.g, o.level, false);
+        ref(a.eout, o.level, true);
+        if (a.inject) ref(a.einj, o.level + 1, true);
+        break;
+    }
+    default:
+        break;
+    }
+    return k;
+}
+
+// Stage one run [i, j) of coarse operations in LDS: every buffer it touches
+// gets an LDS slot; a buffer is loaded when the run reads it before writing
+// it, and stored when the next reference after the run (the cycle repeats,
+// so the search wraps around) is a read.  live_out, the cycle's result, is
+// read at the end of every cycle.  Returns false when the run does
+// not fit (its levels or its LDS image too large, or the staging full).
+template <typename T>
+bool stage_lds_run(sgml_plan *P, const std::vector<HostOp> &ops, const void *live_out, size_t i, size_t j,
+                   int &nl, int &nx, RunDesc &R)
+{
+    struct Slot {
+        const void *p;
+        size_t count;
+        int off;
+        bool load, written;
+    };
+    std::vector<Slot> slots;
+    auto find = [&](const void *p) {
+        for (size_t q = 0; q < slots.size(); ++q)
+            if (slots[q].p == p) return (int)q;
+        return -1;
+    };
+    size_t elems = 0;
+    for (size_t k = i; k < j; ++k) {
+        if (level_nodes(P->dim, P->n, ops[k].op.level) > (size_t)coarse_lds_nodes(P->dim)) return false;
+        Ref r[6];
+        const int nr = op_refs(P, ops[k], r);
+        for (int q = 0; q < nr; ++q) {
+            int s = find(r[q].p);
+            if (s < 0) {
+                slots.push_back({r[q].p, r[q].count, (int)elems, !r[q].write, false});
+                elems += (r[q].count + 3) / 4 * 4;
+                s = (int)slots.size() - 1;
+            }
+            if (r[q].write) slots[s].written = true;
+        }
+    }
+    const size_t ops_off = (elems * sizeof(T) + 15) / 16 * 16;
+    const size_t bytes = ops_off + (j - i) * sizeof(LdsOp);
+    const size_t budget = P->lds_max > 1024 ? P->lds_max - 1024 : 0;  // static LDS of the kernel
+    if (bytes > budget || nl + (j - i) > (size_t)kMaxCoarseOps || nx + 2 * slots.size() > (size_t)kMaxXfers)
+        return false;
+    const size_t nops = ops.size();
+    auto stored = [&](const void *p) {
+        for (size_t d = 0; d < nops; ++d) {
+            if ((j + d) % nops == 0 && p == live_out) return true;
+            Ref r[6];
+            const int nr = op_refs(P, ops[(j + d) % nops], r);
+            for (int q = 0; q < nr; ++q)
+                if (r[q].p == p) return !r[q].write;
+        }
+        return false;
+    };
+    auto off = [&](const void *p) {
+        const int s = find(p);
+        return s < 0 ? 0 : slots[s].off;
+    };
+    R.lds = 1;
+    R.lop0 = nl;
+    R.x0 = nx;
+    R.lds_bytes = bytes;
+    R.ops_off = (int)ops_off;
+    for (size_t k = i; k < j; ++k) {
+        const CoarseOp &o = ops[k].op;
+        LdsOp &lo = P->lops_host[nl++];
+        std::memset(&lo, 0, sizeof(lo));
+        lo.kind = o.kind;
+        lo.m = o.m;
+        lo.first = o.first;
+        lo.target = o.target;
+        lo.in0 = off(o.in0);
+        lo.in1 = off(o.in1);
+        lo.out = off(o.out);
+        lo.nodes = (int)level_nodes(P->dim, P->n, o.level);
+        lo.inv_m = 1.0f / (float)o.m;
+        lo.sig = o.in2;
+        lo.L = P->level(o.level);
+    }
+    R.nload = R.nstore = 0;
+    for (const Slot &sl : slots)
+        if (sl.load) {
+            P->xfer_host[nx++] = {const_cast<void *>(sl.p), sl.off, (int)sl.count};
+            ++R.nload;
+        }
+    for (const Slot &sl : slots)
+        if (sl.written && stored(sl.p)) {
+            P->xfer_host[nx++] = {const_cast<void *>(sl.p), sl.off, (int)sl.count};
+            ++R.nstore;
+        }
+    return true;
+}
+
+// Upload the coarse operations (in execution order), their LDS form and the
+// level table; the device copy serves every cycle of the solve.  Coarse runs
+// beyond the buffer's capacity fall back to separate launches.
+template <typename T>
+sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, const void *live_out, hipStream_t st)
 {
     int nc = 0;
     for (auto &h : ops) {
@@ -408,8 +570,30 @@ sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, hipStream_t st)
         }
         P->ops_host[nc++] = h.op;
     }
+    P->runs.clear();
+    int op0 = 0, nl = 0, nx = 0;
+    for (size_t i = 0; i < ops.size();) {
+        if (!ops[i].coarse) {
+            ++i;
+            continue;
+        }
+        size_t j = i;
+        while (j < ops.size() && ops[j].coarse) ++j;
+        RunDesc R;
+        std::memset(&R, 0, sizeof(R));
+        R.op0 = op0;
+        R.nops = (int)(j - i);
+        if (!stage_lds_run<T>(P, ops, live_out, i, j, nl, nx, R)) R.lds = 0;
+        P->runs.push_back(R);
+        op0 += R.nops;
+        i = j;
+    }
     for (int nu = 0; nu < P->n; ++nu) P->levels_host[nu] = P->level(nu);
     if (nc) SGML_HIP(hipMemcpyAsync(P->at<CoarseOp>(P->lay.ops), P->ops_host, sizeof(CoarseOp) * nc,
+                                    hipMemcpyHostToDevice, st));
+    if (nl) SGML_HIP(hipMemcpyAsync(P->at<LdsOp>(P->lay.lops), P->lops_host, sizeof(LdsOp) * nl,
+                                    hipMemcpyHostToDevice, st));
+    if (nx) SGML_HIP(hipMemcpyAsync(P->at<LdsXfer>(P->lay.xfer), P->xfer_host, sizeof(LdsXfer) * nx,
                                     hipMemcpyHostToDevice, st));
     SGML_HIP(hipMemcpyAsync(P->at<Level>(P->lay.levels), P->levels_host, sizeof(Level) * P->n,
                             hipMemcpyHostToDevice, st));
@@ -424,15 +608,19 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
 {
     const CoarseOp *dev_ops = P->at<CoarseOp>(P->lay.ops);
     const Level *dev_levels = P->at<Level>(P->lay.levels);
+    const LdsOp *dev_lops = P->at<LdsOp>(P->lay.lops);
+    const LdsXfer *dev_xfer = P->at<LdsXfer>(P->lay.xfer);
     unsigned long long *targets = target(P, 0);
-    int coarse_done = 0;
+    size_t run = 0;
     for (size_t i = 0; i < ops.size();) {
         if (ops[i].coarse) {
             size_t j = i;
             while (j < ops.size() && ops[j].coarse) ++j;
-            const int cnt = (int)(j - i);
-            launch_coarse<T>(P->var, dev_ops + coarse_done, cnt, dev_levels, G, targets, st);
-            coarse_done += cnt;
+            if (run >= P->runs.size()) return SGML_E_ARG;
+            const RunDesc &R = P->runs[run++];
+            const bool staged = R.lds && launch_coarse_lds<T>(P->var, dev_lops + R.lop0, R.nops, R.ops_off, dev_xfer + R.x0,
+                                                              R.nload, R.nstore, R.lds_bytes, G, targets, st);
+            if (!staged) launch_coarse<T>(P->var, dev_ops + R.op0, R.nops, dev_levels, G, targets, st);
             i = j;
             continue;
         }
@@ -446,7 +634,10 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             const int cls = a.inject ? SGML_PROF_VISIT0_INJ : SGML_PROF_VISIT0;
             hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
             if (ev) SGML_HIP(hipEventRecord(ev[0], st));
-            launch_visit2d<T>(P->var, a, st);
+            if (o.level > 0 && tile_visit_supported(o.m))
+                launch_visit_tile<T>(P->var, a, st);
+            else
+                launch_visit2d<T>(P->var, a, st);
             if (ev) {
                 SGML_HIP(hipEventRecord(ev[1], st));
                 timed.push_back({cls, a.sweeps, ev});
@@ -533,15 +724,22 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
     } else {
         std::vector<HostOp> ops;
         long long updates_per_cycle = 0;
+        const bool z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N);
+        const bool row_march = P->dim == 2 && o->fuse >= 0 && P->N >= 64;
+        // the 2D row-marching cycle end of the mixed cycle also restricts the
+        // new source to level 1; it then writes the residual to the other buffer
+        T *g1 = mixed && row_march && P->n >= 2 ? P->at<T>(P->lay.g[1]) : nullptr;
+        double *s_next = g1 ? P->at<double>(P->lay.s2) : s;
         const T *e = compile_cycle<T>(P, src0, lev, cnt, o->record_pres != 0,
                                       coarse_level_of(P, o->coarse_nodes),
-                                      o->fuse < 0 ? 0 : (o->fuse == 0 ? kDefaultFuseMin : std::max(o->fuse, 64)), ops,
-                                      updates_per_cycle);
-        rc = upload_ops(P, ops, st);
+                                      o->fuse < 0 ? 0 : (o->fuse == 0 ? kDefaultFuseMin : std::max(o->fuse, 64)),
+                                      g1 != nullptr, ops, updates_per_cycle);
+        rc = upload_ops<T>(P, ops, e, st);
         if (rc != SGML_OK) return rc;
         const int chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
         int k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
         if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
+        if (g1) launch_restrict<T, T>(P->dim, P->m(1), src0, g1, st);  // cycle 0's level-1 source
         double last = norm0;
         for (int i = 0; i < o->max_cycles; ++i) {
             const double *Gc = i == 0 ? G : nullptr;
@@ -556,8 +754,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             const int k_next = mixed ? std::ilogb(last) : 0;
             hipEvent_t *ev = o->profile ? prof_pair(P) : nullptr;
             if (ev) SGML_HIP(hipEventRecord(ev[0], st));
-            const bool z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N);
-            if ((P->dim == 2 && o->fuse >= 0 && P->N >= 64) || z_march) {
+            if (row_march || z_march) {
                 CycleEndArgs ca;
                 ca.e = e;
                 ca.escale = std::ldexp(1.0, k_cur);
@@ -565,9 +762,11 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                 ca.sigma = P->sigma;
                 ca.u = u;
                 ca.s = s;
+                ca.s_out = s_next;
                 ca.shat = shat;
                 ca.shat_scale = std::ldexp(1.0, -k_next);
                 ca.norm = target(P, 0);
+                ca.g1 = g1;
                 ca.L = L0;
                 ca.chunk = chunk;
                 if (z_march)
@@ -599,6 +798,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             if (i < SGML_HIST) S.history[i] = rel;
             k_cur = k_next;
             last = norm;
+            std::swap(s, s_next);  // the residual the next cycle end reads
             if (!std::isfinite(rel) || rel > 1e3) {
                 status = SGML_E_DIVERGED;
                 break;
@@ -683,13 +883,23 @@ sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *work
         return SGML_E_HIP;
     }
     P->ops_host = nullptr;
+    P->lops_host = nullptr;
+    P->xfer_host = nullptr;
     P->levels_host = nullptr;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) != hipSuccess) lds = 0;
+    P->lds_max = lds > 0 ? (size_t)lds : 0;
     if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess ||
         hipHostMalloc((void **)&P->ops_host, sizeof(CoarseOp) * kMaxCoarseOps, hipHostMallocDefault) !=
             hipSuccess ||
+        hipHostMalloc((void **)&P->lops_host, sizeof(LdsOp) * kMaxCoarseOps, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&P->xfer_host, sizeof(LdsXfer) * kMaxXfers, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&P->levels_host, sizeof(Level) * kMaxLevels, hipHostMallocDefault) !=
             hipSuccess) {
         if (P->ops_host) (void)hipHostFree(P->ops_host);
+        if (P->lops_host) (void)hipHostFree(P->lops_host);
+        if (P->xfer_host) (void)hipHostFree(P->xfer_host);
         (void)hipHostFree(P->host);
         delete P;
         return SGML_E_HIP;
@@ -813,6 +1023,8 @@ void sgml_plan_destroy(sgml_plan *P)
     (void)hipEventDestroy(P->ev1);
     for (hipEvent_t e : P->pev) (void)hipEventDestroy(e);
     (void)hipHostFree(P->ops_host);
+    (void)hipHostFree(P->lops_host);
+    (void)hipHostFree(P->xfer_host);
     (void)hipHostFree(P->levels_host);
     (void)hipHostFree(P->host);
     delete P;

@@ -318,10 +318,23 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
 // values replaced by G (first cycle) or 0.  Same strip/row marching as the
 // visit: e is read once per node, its vertical neighbours come from a
 // three-row window and the horizontal ones from the adjacent lanes.
-template <typename T, int RAD, int SIG>
+//
+// RES: the pass also writes the next cycle's level-1 source, the first step
+// of the restriction pyramid (Algorithm 1, eq. (3)) of the new source (shat,
+// or s itself in FP64).  Level-1 node (I, J) averages the source at fine
+// rows 2J-1 .. 2J+1 and columns 2I-1 .. 2I+1 (images outside the grid).
+// For that a wavefront computes the source one column beyond its strip on
+// each side (halo of two) and one row above its chunk (chunks start at even
+// rows), keeps the last three rows per lane, and on each odd row r
+// completes level-1 row (r-1)/2: vertical weights (1/2, 1, 1/2) in the
+// lane, horizontal ones across lanes, over 4.  It writes the level-1 nodes
+// whose centre it owns.  The halo nodes belong to other wavefronts, which
+// write their new residual meanwhile: with RES the new residual goes to
+// s_out, a second buffer, and s is only read.
+template <typename T, int RAD, int SIG, int RES>
 __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
 {
-    constexpr int HX = 1;
+    constexpr int HX = RES ? 2 : 1;
     constexpr int W = 64 - 2 * HX;
     const Level L = A.L;
     const int m = L.m;
@@ -336,17 +349,25 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     const int x = sx * W - HX + lane;
     const int xm = mir(x, m);
     const bool xout = lane >= HX && lane < HX + W && x < m;
+    // lanes whose source value the restriction reads (owned columns and one on each side)
+    const bool xsrc = RES && lane >= 1 && lane < 63;
     const bool xdir = ((L.dir & 1u) && xm == 0) || ((L.dir & 2u) && xm == m - 1);
     const T *__restrict__ E = (const T *)A.e;
     const double *__restrict__ G = A.G;
     const double *__restrict__ sig = A.sigma;
     double *__restrict__ u = A.u;
-    double *__restrict__ sres = A.s;
+    const double *__restrict__ sres = A.s;
+    double *__restrict__ sout = RES ? A.s_out : A.s;
     T *__restrict__ shat = (T *)A.shat;
+    T *__restrict__ g1 = (T *)A.g1;
+    const int m1 = (m + 1) / 2;
     const double scale = L.scale, a = L.a, escale = A.escale;
-
-    const int rows = (y1 - y0) + 2;
+    // first output row: one above the chunk when restricting (for the
+    // level-1 row centred on the chunk's first row)
+    const int r_first = RES ? max(y0 - 1, 0) : y0;
+    const int rows = (y1 - y0) + 2 + RES;
     double w[3] = {0.0, 0.0, 0.0}, sw[3] = {1.0, 1.0, 1.0};
+    T hs[3] = {T(0), T(0), T(0)};  // source at output rows r-2, r-1, r (RES)
     unsigned long long nb = 0;
     // raw loads of input row rho (e, coefficient) and of output row rho - 1 (s, u)
     struct Raw {
@@ -354,18 +375,20 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
         double sg, s, u;
     };
     auto load = [&](Raw &R, int t) {
-        const int rho = y0 - 1 + t;
+        const int rho = y0 - 1 - RES + t;
         const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m;
         R.e = ld(E, rm * um + (unsigned)xm);
         if (SIG) R.sg = ld(sig, rm * um + (unsigned)xm);
         const int r = rho - 1;
-        if (r >= y0 && r < y1 && xout) {
-            R.s = ld((const double *)sres, (unsigned)r * um + (unsigned)x);
-            R.u = ld((const double *)u, (unsigned)r * um + (unsigned)x);
+        R.s = 0.0;
+        R.u = 0.0;
+        if (r >= r_first && r < y1) {
+            if (xout || xsrc) R.s = ld(sres, (unsigned)r * um + (unsigned)xm);
+            if (xout && r >= y0) R.u = ld((const double *)u, (unsigned)r * um + (unsigned)x);
         }
     };
     auto step_row = [&](const Raw &R, int t) {
-        const int rho = y0 - 1 + t, rm = mir(rho, m);
+        const int rho = y0 - 1 - RES + t, rm = mir(rho, m);
         const bool ydir_in = ((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1);
         double ev = escale * (double)R.e;
         if (xdir || ydir_in) ev = G ? ld(G, (unsigned)rm * (unsigned)m + (unsigned)xm) : 0.0;  // Dirichlet values
@@ -403,19 +426,42 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
             }
             Le = scale * acc + a * c;
         }
-        if (t >= 2 && r >= y0 && r < y1 && xout) {
-            const bool ydir = ((L.dir & 4u) && r == 0) || ((L.dir & 8u) && r == m - 1);
+        if (t < 2 || r < r_first || r >= y1) return;  // uniform: rows outside the chunk
+        const bool ydir = ((L.dir & 4u) && r == 0) || ((L.dir & 8u) && r == m - 1);
+        const bool dirn = xdir || ydir;
+        const double snew = dirn ? 0.0 : R.s - Le;
+        const T sh = shat ? (T)(snew * A.shat_scale) : (T)snew;  // next cycle's source
+        if (xout && r >= y0) {
             const unsigned q = (unsigned)r * (unsigned)m + (unsigned)x;
             st(u, q, R.u + c);
-            if (xdir || ydir) {
-                st(sres, q, 0.0);
-                if (shat) st(shat, q, T(0));
-            } else {
-                const double snew = R.s - Le;
-                st(sres, q, snew);
-                if (shat) st(shat, q, (T)(snew * A.shat_scale));
+            st(sout, q, snew);
+            if (shat) st(shat, q, sh);
+            if (!dirn) {
                 const unsigned long long b = dbits(snew);
                 nb = b > nb ? b : nb;
+            }
+        }
+        if (RES) {
+            hs[0] = hs[1];
+            hs[1] = hs[2];
+            hs[2] = sh;
+            // level-1 row J: fine rows 2J-1, 2J, 2J+1 (images at the faces)
+            int J = -1;
+            T up = hs[0], mid = hs[1], dn = hs[2];
+            if ((r & 1) && r - 1 >= y0) {
+                J = (r - 1) / 2;
+                if (r == 1) up = dn;  // row -1 is the image of row 1
+            } else if (!(r & 1) && r == m - 1) {
+                J = r / 2;  // last row: row m is the image of row m - 2
+                up = hs[1];
+                mid = hs[2];
+                dn = hs[1];
+            }
+            if (J >= 0) {
+                const T v = T(0.5) * up + mid + T(0.5) * dn;
+                const T vl = from_left(v), vr = from_right(v);
+                const T res = (T(0.5) * vl + v + T(0.5) * vr) * T(0.25);
+                if (xout && !(x & 1)) st(g1, (unsigned)J * (unsigned)m1 + (unsigned)(x >> 1), res);
             }
         }
     };
@@ -500,17 +546,27 @@ void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st
 {
     CycleEndArgs a = a0;
     const int m = a.L.m;
+    const bool res = a.g1 != nullptr && a.s_out != nullptr && a.s_out != a.s;
     a.chunk = a0.chunk > 0 ? a0.chunk : 32;
-    const long long waves = (long long)((m + 61) / 62) * ((m + a.chunk - 1) / a.chunk);
+    if (res) a.chunk = (a.chunk + 1) & ~1;  // chunks start at even rows
+    const int W = res ? 60 : 62;
+    const long long waves = (long long)((m + W - 1) / W) * ((m + a.chunk - 1) / a.chunk);
     const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
-    if (v.radial && v.sigma)
-        hipLaunchKernelGGL((k_cycle_end2d<T, 1, 1>), grid, block, 0, st, a);
-    else if (v.radial)
-        hipLaunchKernelGGL((k_cycle_end2d<T, 1, 0>), grid, block, 0, st, a);
-    else if (v.sigma)
-        hipLaunchKernelGGL((k_cycle_end2d<T, 0, 1>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_cycle_end2d<T, 0, 0>), grid, block, 0, st, a);
+#define SGML_CE(R, S)                                                                       \
+    if (res)                                                                                \
+        hipLaunchKernelGGL((k_cycle_end2d<T, R, S, 1>), grid, block, 0, st, a);             \
+    else                                                                                    \
+        hipLaunchKernelGGL((k_cycle_end2d<T, R, S, 0>), grid, block, 0, st, a);
+    if (v.radial && v.sigma) {
+        SGML_CE(1, 1)
+    } else if (v.radial) {
+        SGML_CE(1, 0)
+    } else if (v.sigma) {
+        SGML_CE(0, 1)
+    } else {
+        SGML_CE(0, 0)
+    }
+#undef SGML_CE
 }
 
 template void launch_cycle_end2d<double>(const Variant &, const CycleEndArgs &, hipStream_t);

@@ -69,6 +69,8 @@ struct LdsOp {
     int out;          // element offset of the result
     int nodes;        // m^d
     float inv_m;      // 1 / m in float
+    int solo;         // run by wavefront 0 alone (a small level, no reduction target)
+    int sync;         // a workgroup barrier follows (every operation but a solo one before another)
     int pad;
     const void *sig;  // sweeps: level coefficient (global memory) or null
     Level L;          // sweeps: constants of the level

@@ -411,6 +411,13 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse(const CoarseOp *
 // computes all of them before storing any, so the loads of a thread issue
 // together.  Each operation reads one buffer of a level and writes the other
 // (or another level), as in k_coarse.
+//
+// Operations on small levels (at most one node per lane of a wavefront,
+// flagged solo by the host) run on wavefront 0 alone, back to back, ordered
+// by waiting on its own LDS accesses; the other wavefronts skip them and
+// meet wavefront 0 at the barrier that closes the section (op.sync).  A
+// barrier costs every wavefront's issue slots, and on these levels one
+// wavefront has all the parallelism there is.
 template <typename T, int DIM, int RAD, int SIG>
 __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp *__restrict__ ops, int nops,
                                                                int ops_off, const LdsXfer *__restrict__ xfer,
@@ -439,6 +446,7 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
     }
     __syncthreads();
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // first node of this wave
+    const int lane = tid & 63;
     for (int o = 0; o < nops; ++o) {
         const LdsOp &op = sops[o];
         // uniform over the workgroup: the fields the control flow uses go to scalars
@@ -446,8 +454,12 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
         const int m = __builtin_amdgcn_readfirstlane(op.m);
         const int nodes = __builtin_amdgcn_readfirstlane(op.nodes);
         const int target = __builtin_amdgcn_readfirstlane(op.target);
+        const int solo = __builtin_amdgcn_readfirstlane(op.solo);
+        const int sync = __builtin_amdgcn_readfirstlane(op.sync);
+        // nodes of this thread: base, base + stride, ...; first: of the wave
+        const int base = solo ? lane : tid, stride = solo ? 64 : NT, first_node = solo ? 0 : wbase;
         unsigned long long rb = 0;
-        if (wbase < nodes) {  // waves past the level's last node only meet the barrier
+        if (solo ? wbase == 0 : wbase < nodes) {  // the other waves only meet the barrier
             const float inv = op.inv_m;
             const int in0 = __builtin_amdgcn_readfirstlane(op.in0);
             const int in1 = __builtin_amdgcn_readfirstlane(op.in1);
@@ -470,8 +482,8 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
             auto each = [&](auto f) {
 #pragma unroll
                 for (int q = 0; q < KMAX; ++q) {
-                    const int t = tid + q * NT;
-                    if (wbase + q * NT < nodes && t < nodes) {
+                    const int t = base + q * stride;
+                    if (first_node + q * stride < nodes && t < nodes) {
                         int i, j, k;
                         decode(t, i, j, k);
                         val[q] = f(t, i, j, k);
@@ -489,9 +501,32 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
                 K.theta = (T)L.theta;
                 K.step = K.theta / const_diag<T, DIM, RAD>(K.scale, K.a);
                 const bool want_rb = target >= 0;
-                each([&](int, int i, int j, int k) {
-                    return lds_sweep_value<T, DIM, RAD, SIG>(ein, g, sig, G, L, K, i, j, k, want_rb, rb);
-                });
+                if (DIM == 2 && !RAD && !SIG) {
+                    // 5-point, sigma = 1: e' = (1 - theta) e + beta (sum of neighbours) - gamma g,
+                    // beta = theta scale / D, gamma = theta / D; images at the faces
+                    const T Dc = const_diag<T, DIM, RAD>(K.scale, K.a);
+                    const T omt = T(1) - K.theta, beta = K.theta * K.scale / Dc, gamma = K.theta / Dc;
+                    const T aw = K.a - T(4) * K.scale;
+                    const unsigned dir = L.dir;
+                    each([&](int t, int i, int j, int) {
+                        const int il = i > 0 ? t - 1 : t + 1, ir = i < m - 1 ? t + 1 : t - 1;
+                        const int ju = j > 0 ? t - m : t + m, jd = j < m - 1 ? t + m : t - m;
+                        const T c = ein[t], gt = g[t];
+                        const T sum = (ein[il] + ein[ir]) + (ein[ju] + ein[jd]);
+                        const bool d = (((dir & 1u) != 0) & (i == 0)) | (((dir & 2u) != 0) & (i == m - 1)) |
+                                       (((dir & 4u) != 0) & (j == 0)) | (((dir & 8u) != 0) & (j == m - 1));
+                        if (want_rb && !d) {
+                            const unsigned long long b = dbits((double)(K.scale * sum + aw * c - gt));
+                            rb = b > rb ? b : rb;
+                        }
+                        if (d) return G ? (T)G[lin(i * L.lam, j * L.lam, 0, L.N)] : T(0);
+                        return omt * c + (beta * sum - gamma * gt);
+                    });
+                } else {
+                    each([&](int, int i, int j, int k) {
+                        return lds_sweep_value<T, DIM, RAD, SIG>(ein, g, sig, G, L, K, i, j, k, want_rb, rb);
+                    });
+                }
                 break;
             }
             case kOpProlong: {
@@ -518,12 +553,15 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
             T *out = sm + __builtin_amdgcn_readfirstlane(op.out);
 #pragma unroll
             for (int q = 0; q < KMAX; ++q) {
-                const int t = tid + q * NT;
-                if (wbase + q * NT < nodes && t < nodes) out[t] = val[q];
+                const int t = base + q * stride;
+                if (first_node + q * stride < nodes && t < nodes) out[t] = val[q];
             }
         }
-        if (kind == kOpSweep && target >= 0) block_max(rb, targets + (size_t)target * kRedWords);
-        __syncthreads();
+        if (kind == kOpSweep && target >= 0) block_max(rb, targets + (size_t)target * kRedWords);  // not solo
+        if (sync)
+            __syncthreads();
+        else  // solo, within a section: wavefront 0's writes complete before its next reads
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     }
     for (int x = nload; x < nload + nstore; ++x) {
         T *dst = static_cast<T *>(xfer[x].ptr);

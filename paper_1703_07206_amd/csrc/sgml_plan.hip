@@ -538,9 +538,14 @@ bool stage_lds_run(sgml_plan *P, const std::vector<HostOp> &ops, const void *liv
         lo.out = off(o.out);
         lo.nodes = (int)level_nodes(P->dim, P->n, o.level);
         lo.inv_m = 1.0f / (float)o.m;
+        // small levels: one wavefront, one node per lane
+        lo.solo = lo.nodes <= 64 && o.target < 0;
+        lo.sync = 1;
         lo.sig = o.in2;
         lo.L = P->level(o.level);
     }
+    for (int q = R.lop0; q + 1 < nl; ++q)  // a solo operation followed by another needs no barrier
+        if (P->lops_host[q].solo && P->lops_host[q + 1].solo) P->lops_host[q].sync = 0;
     R.nload = R.nstore = 0;
     for (const Slot &sl : slots)
         if (sl.load) {

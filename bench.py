@@ -56,7 +56,7 @@ def copy_calibration():
 
 
 def kernel_source_hash():
-    src = os.path.join(ROOT, "paper_1703_07206_amd", "csrc", "sgml_visit2d.hip")
+    src = os.path.join(ROOT, "paper_1703_07206_amd", "csrc", "sgml_visit2d_impl.h")
     with open(src, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 

@@ -3,7 +3,7 @@
 // A visit of Algorithm 3 at level nu: interpolate the pending variation of
 // level nu+1 (when the schedule refines), run c relaxations (Algorithm 2,
 // Jacobi), copy the result to level nu+1's nodes (when the schedule climbs).
-// The row-marching visit (sgml_visit2d.hip) streams a level through
+// The row-marching visit (sgml_visit2d_impl.h) streams a level through
 // registers, which suits the 4097^2 level 0; on the smaller levels its
 // wavefronts are few and each one's row chain is long, so the visit is
 // latency bound.  Here a workgroup takes a 64 x 32 tile of the level plus a

@@ -1,20 +1,24 @@
-// sgml_visit2d.hip -- one visit of a 2D level in one pass over memory.
+// sgml_visit2d_impl.h -- one visit of a 2D level in one pass over memory
+// (included by sgml_visit2d_f32.hip and sgml_visit2d_f64.hip, which
+// instantiate it for one precision each).
 //
 // A visit of Algorithm 3 at level nu is: interpolate the pending variation of
 // level nu+1 (when the schedule refines), run c relaxations (Algorithm 2,
 // Jacobi), and copy the result to level nu+1's nodes (when the schedule
 // climbs).  Run one launch per step and each relaxation streams the level
-// through HBM again.  Here every wavefront owns a strip of 64 columns and
-// marches down the rows of a chunk; each relaxation is a pipeline stage that
-// keeps a three-row window of its input in registers, so relaxation s+1
-// consumes relaxation s's rows as they are produced.  Horizontal neighbours
-// come from the adjacent lanes (cross-lane moves), vertical ones from the
-// window.  The strip and the chunk carry a halo as wide as the number of
+// through HBM again.  Here every wavefront owns a strip of 128 columns, two
+// per lane, and marches down the rows of a chunk; each relaxation is a
+// pipeline stage that keeps a three-row window of its input in registers, so
+// relaxation s+1 consumes relaxation s's rows as they are produced.
+// Horizontal neighbours come from the lane's other column or the adjacent
+// lane (cross-lane moves), vertical ones from the window.  The strip and the chunk carry a halo as wide as the number of
 // relaxations (plus one column for the interpolation), recomputed by the
 // neighbouring wavefronts; only the interior is written.  Values outside the
 // grid are images (node reflection), so Neumann faces need no special case,
 // and a Dirichlet node takes its prescribed value at every relaxation.
 // Wavefronts are independent: no LDS, no barriers.
+#pragma once
+
 #include "sgml_device.h"
 
 #include <type_traits>
@@ -78,121 +82,156 @@ struct RelaxK {
     T scale, a, theta, omt, beta, gamma, aw;  // aw = a - W scale
 };
 
-// One relaxation of the node in the middle row of the window w (rows r-1,
-// r, r+1 of this lane's column); sg: the coefficient in the same rows.  All
-// lanes must call it (cross-lane moves).
-template <typename T, int RAD, int SIG, int REC>
-__device__ __forceinline__ T relax(const T (&w)[3], const T (&sg)[3], T g, bool dir, T gval, const RelaxK<T> &K,
-                                   T &resid)
-{
-    const T c = w[1];
-    const T ul = from_left(c), ur = from_right(c);
-    T nl = T(0), nr = T(0), sl = T(0), sr = T(0);  // corner values (radial)
-    if (RAD) {
-        nl = from_left(w[0]);
-        nr = from_right(w[0]);
-        sl = from_left(w[2]);
-        sr = from_right(w[2]);
-    }
-    if (SIG) {
-        const T sc = sg[1];
-        const T tl = from_left(sc) + sc, tr = from_right(sc) + sc;
-        const T tn = sg[0] + sc, ts = sg[2] + sc;
-        T acc = tl * (ul - c) + tr * (ur - c) + tn * (w[0] - c) + ts * (w[2] - c);
-        T ds = tl + tr + tn + ts;
-        if (RAD) {
-            const T tnl = from_left(sg[0]) + sc, tnr = from_right(sg[0]) + sc;
-            const T tsl = from_left(sg[2]) + sc, tsr = from_right(sg[2]) + sc;
-            acc += T(0.5) * (tnl * (nl - c) + tnr * (nr - c) + tsl * (sl - c) + tsr * (sr - c));
-            ds += T(0.5) * (tnl + tnr + tsl + tsr);
-        }
-        const T r = K.scale * T(0.5) * acc + K.a * c - g;
-        if (REC) resid = dir ? T(0) : r;
-        return dir ? gval : c + step_of(K.theta, K.scale * T(0.5) * ds - K.a) * r;
-    }
-    T sum = (ul + ur) + (w[0] + w[2]);
-    if (RAD) sum += T(0.5) * ((nl + nr) + (sl + sr));
-    if (REC) resid = dir ? T(0) : K.scale * sum + K.aw * c - g;
-    return dir ? gval : K.omt * c + (K.beta * sum - K.gamma * g);
-}
+// Lane l of a strip holds the column pair (x, x + 1), x even.  The left neighbour of x and the right
+// neighbour of x + 1 come from the adjacent lanes (one cross-lane move each
+// per row and relaxation, for two nodes); the row and pipeline bookkeeping,
+// which is per row and per wavefront, serves twice the nodes; a strip is 128
+// columns wide with an even halo, so 128 - 2 * HX of them are written.
 
-// The raw loads of one input row: the level's stale value, the source, the
-// coefficient and, for the interpolation, the next coarser level's values
-// and the stale values at its nodes (even columns only) in the coarse rows
-// Y = rm/2 and Y + 1 (odd rows).  Issued a few rows ahead of their use.
 template <typename T>
-struct RowIn {
-    T st, g, sg, c0, c1, s0, s1;
+struct RowIn2 {
+    T sta, stb, ga, gb, sga, sgb, c0, c1, s0, s1;
 };
 
 template <typename T, int PRO, int SIG>
-__device__ __forceinline__ void load_row(RowIn<T> &R, const VisitArgs &A, int xm, int rho, int m)
+__device__ __forceinline__ void load_row2(RowIn2<T> &R, const VisitArgs &A, int xma, int xmb, int rho, int m)
 {
-    // unsigned 32-bit element offsets (2D levels: m^2 < 2^31): a scalar base
-    // plus a per-lane offset, no 64-bit address arithmetic per lane
-    const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m, ux = (unsigned)xm;
+    const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m;
     const unsigned row = rm * um;
     const T *__restrict__ estale = (const T *)A.estale;
-    R.st = (PRO && A.first) ? T(0) : ld(estale, row + ux);
-    R.g = ld((const T *)A.g, row + ux);
-    if (SIG) R.sg = ld((const T *)A.sig, row + ux);
+    const T *__restrict__ g = (const T *)A.g;
+    if (PRO && A.first) {
+        R.sta = R.stb = T(0);
+    } else {
+        R.sta = ld(estale, row + (unsigned)xma);
+        R.stb = ld(estale, row + (unsigned)xmb);
+    }
+    R.ga = ld(g, row + (unsigned)xma);
+    R.gb = ld(g, row + (unsigned)xmb);
+    if (SIG) {
+        const T *__restrict__ sig = (const T *)A.sig;
+        R.sga = ld(sig, row + (unsigned)xma);
+        R.sgb = ld(sig, row + (unsigned)xmb);
+    }
     if (PRO) {
+        // coarse node X = xma / 2 (xma is even), rows Y = rm / 2 and Y + 1
         const T *__restrict__ ec = (const T *)A.ecoarse;
-        const unsigned mc = (um + 1) >> 1, Y = rm >> 1;
-        R.c0 = R.c1 = R.s1 = T(0);
-        R.s0 = R.st;
-        if (!(ux & 1)) {
-            R.c0 = ld(ec, Y * mc + (ux >> 1));
-            if (rm & 1) {
-                R.c1 = ld(ec, (Y + 1) * mc + (ux >> 1));
-                if (!A.first) {
-                    R.s0 = ld(estale, 2 * Y * um + ux);
-                    R.s1 = ld(estale, (2 * Y + 2) * um + ux);
-                }
+        const unsigned mc = (um + 1) >> 1, Y = rm >> 1, X = (unsigned)xma >> 1;
+        R.c0 = ld(ec, Y * mc + X);
+        R.c1 = R.s1 = T(0);
+        R.s0 = R.sta;  // even rows: the stale value at the coarse node is this row's
+        if (rm & 1) {
+            R.c1 = ld(ec, (Y + 1) * mc + X);
+            if (!A.first) {
+                R.s0 = ld(estale, 2 * Y * um + (unsigned)xma);
+                R.s1 = ld(estale, (2 * Y + 2) * um + (unsigned)xma);
+            } else {
+                R.s0 = T(0);
             }
         }
     }
 }
 
-// The level's value at (rm, xm) with the pending variation of the next
-// coarser level interpolated: coarse nodes take the coarse value, the others
-// add the tensor-hat mean of the pending variation (coarse value minus stale
-// finer value) of the enclosing coarse nodes.  rm is the same in every lane;
-// all lanes must call it (cross-lane moves).
+// The level's values at (rm, x) and (rm, x + 1) with the pending variation
+// of the next coarser level interpolated: coarse nodes take the coarse
+// value, the others add the tensor-hat mean of the pending variation (coarse
+// value minus stale finer value) of the enclosing coarse nodes.  x is a coarse
+// column, x + 1 lies between coarse columns x / 2 and x / 2 + 1, the latter
+// held by the next lane.  All lanes must call it.
 template <typename T>
-__device__ __forceinline__ T prolonged(const RowIn<T> &R, int xm, int rm)
+__device__ __forceinline__ void prolonged2(const RowIn2<T> &R, int rm, T &va, T &vb)
 {
-    const bool xe = !(xm & 1);
-    auto along_x = [&](T p) -> T {  // pending variation interpolated along x
-        const T pl = from_left(p), pr = from_right(p);
-        return xe ? p : T(0.5) * (pl + pr);
-    };
     if (!(rm & 1)) {
-        const T p = along_x(xe ? R.c0 - R.s0 : T(0));
-        return xe ? R.c0 : R.st + p;
+        const T p = R.c0 - R.s0;
+        const T pr = from_right(p);
+        va = R.c0;
+        vb = R.stb + T(0.5) * (p + pr);
+    } else {
+        const T p0 = R.c0 - R.s0, p1 = R.c1 - R.s1;
+        const T p0r = from_right(p0), p1r = from_right(p1);
+        va = R.sta + T(0.5) * (p0 + p1);
+        vb = R.stb + T(0.5) * (T(0.5) * (p0 + p0r) + T(0.5) * (p1 + p1r));
     }
-    const T p0 = along_x(xe ? R.c0 - R.s0 : T(0)), p1 = along_x(xe ? R.c1 - R.s1 : T(0));
-    return R.st + T(0.5) * (p0 + p1);
+}
+
+// One relaxation of the column pair in the middle row of the windows wa, wb
+// (rows r-1, r, r+1); sa, sb: the coefficient there.  All lanes must call it.
+template <typename T, int RAD, int SIG, int REC>
+__device__ __forceinline__ void relax2(const T (&wa)[3], const T (&wb)[3], const T (&sa)[3], const T (&sb)[3], T ga,
+                                       T gb, bool da, bool db, T gva, T gvb, const RelaxK<T> &K, T &na, T &nb,
+                                       T &resa, T &resb)
+{
+    const T ca = wa[1], cb = wb[1];
+    const T la = from_left(cb), rb = from_right(ca);  // left of x, right of x + 1
+    T ula = T(0), dla = T(0), urb = T(0), drb = T(0);  // corners across the lane boundary (radial)
+    if (RAD) {
+        ula = from_left(wb[0]);
+        dla = from_left(wb[2]);
+        urb = from_right(wa[0]);
+        drb = from_right(wa[2]);
+    }
+    if (SIG) {
+        const T sca = sa[1], scb = sb[1];
+        // column x: left (la), right (cb), up, down
+        const T tla = from_left(scb) + sca, tra = scb + sca, tna = sa[0] + sca, tsa = sa[2] + sca;
+        T acca = tla * (la - ca) + tra * (cb - ca) + tna * (wa[0] - ca) + tsa * (wa[2] - ca);
+        T dsa = tla + tra + tna + tsa;
+        // column x + 1: left (ca), right (rb), up, down
+        const T tlb = sca + scb, trb = from_right(sca) + scb, tnb = sb[0] + scb, tsb = sb[2] + scb;
+        T accb = tlb * (ca - cb) + trb * (rb - cb) + tnb * (wb[0] - cb) + tsb * (wb[2] - cb);
+        T dsb = tlb + trb + tnb + tsb;
+        if (RAD) {
+            const T tnla = from_left(sb[0]) + sca, tnra = sb[0] + sca;
+            const T tsla = from_left(sb[2]) + sca, tsra = sb[2] + sca;
+            acca += T(0.5) * (tnla * (ula - ca) + tnra * (wb[0] - ca) + tsla * (dla - ca) + tsra * (wb[2] - ca));
+            dsa += T(0.5) * (tnla + tnra + tsla + tsra);
+            const T tnlb = sa[0] + scb, tnrb = from_right(sa[0]) + scb;
+            const T tslb = sa[2] + scb, tsrb = from_right(sa[2]) + scb;
+            accb += T(0.5) * (tnlb * (wa[0] - cb) + tnrb * (urb - cb) + tslb * (wa[2] - cb) + tsrb * (drb - cb));
+            dsb += T(0.5) * (tnlb + tnrb + tslb + tsrb);
+        }
+        const T ra = K.scale * T(0.5) * acca + K.a * ca - ga;
+        const T rbr = K.scale * T(0.5) * accb + K.a * cb - gb;
+        if (REC) {
+            resa = da ? T(0) : ra;
+            resb = db ? T(0) : rbr;
+        }
+        na = da ? gva : ca + step_of(K.theta, K.scale * T(0.5) * dsa - K.a) * ra;
+        nb = db ? gvb : cb + step_of(K.theta, K.scale * T(0.5) * dsb - K.a) * rbr;
+        return;
+    }
+    T suma = (la + cb) + (wa[0] + wa[2]);
+    T sumb = (ca + rb) + (wb[0] + wb[2]);
+    if (RAD) {
+        suma += T(0.5) * ((ula + wb[0]) + (dla + wb[2]));
+        sumb += T(0.5) * ((wa[0] + urb) + (wa[2] + drb));
+    }
+    if (REC) {
+        resa = da ? T(0) : K.scale * suma + K.aw * ca - ga;
+        resb = db ? T(0) : K.scale * sumb + K.aw * cb - gb;
+    }
+    na = da ? gva : K.omt * ca + (K.beta * suma - K.gamma * ga);
+    nb = db ? gvb : K.omt * cb + (K.beta * sumb - K.gamma * gb);
 }
 
 template <typename T, int RAD, int SIG, int S, int PRO, int REC>
 __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
 {
-    constexpr int HX = S + PRO;     // halo columns on each side of a strip
-    constexpr int W = 64 - 2 * HX;  // columns a wavefront writes
+    constexpr int HX = (S + PRO + 1) / 2 * 2;  // halo columns on each side, even
+    constexpr int W = 128 - 2 * HX;            // columns a wavefront writes
     const Level L = A.L;
     const int m = L.m;
     const int lane = threadIdx.x & 63;
     const int strips = (m + W - 1) / W;
-    // wavefront index, known to be uniform: row and strip arithmetic stays scalar
     const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sx = wid % strips, sy = wid / strips;
     const int y0 = sy * A.chunk;
     if (y0 >= m) return;  // the whole wavefront: past the last chunk
     const int y1 = min(m, y0 + A.chunk);
-    const int x = sx * W - HX + lane;
-    const int xm = mir(x, m);
-    const bool xout = lane >= HX && lane < HX + W && x < m;
+    const int xa = sx * W - HX + 2 * lane;  // even
+    const int xma = mir(xa, m), xmb = mir(xa + 1, m);
+    const bool lane_out = lane >= HX / 2 && lane < (HX + W) / 2;
+    const bool outa = lane_out && xa < m, outb = lane_out && xa + 1 < m;
 
     T *__restrict__ eout = (T *)A.eout;
     T *__restrict__ einj = (T *)A.einj;
@@ -201,86 +240,112 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     K.a = (T)L.a;
     K.theta = (T)L.theta;
     {
-        const double W = RAD ? 6.0 : 4.0, D = W * L.scale - L.a;
+        const double Wd = RAD ? 6.0 : 4.0, D = Wd * L.scale - L.a;
         K.omt = (T)(1.0 - L.theta);
         K.beta = (T)(L.theta * L.scale / D);
         K.gamma = (T)(L.theta / D);
-        K.aw = (T)(L.a - W * L.scale);
+        K.aw = (T)(L.a - Wd * L.scale);
     }
     const bool inject = A.inject != 0;
-    // Dirichlet faces: the x part is fixed per lane, the y part per row
-    const bool xdir = ((L.dir & 1u) && xm == 0) || ((L.dir & 2u) && xm == m - 1);
+    const bool xda = ((L.dir & 1u) && xma == 0) || ((L.dir & 2u) && xma == m - 1);
+    const bool xdb = ((L.dir & 1u) && xmb == 0) || ((L.dir & 2u) && xmb == m - 1);
     const double *__restrict__ G = A.G;
-    const int glane = xm * L.lam, gpitch = L.lam * L.N;
+    const int gpitch = L.lam * L.N;
 
-    T w[S][3];
-    T gh[S + 1];  // gh[k]: source at input row - k
-    T sh[S + 2];  // sh[k]: coefficient at input row - k
+    T wa[S][3], wb[S][3];
+    T gha[S + 1], ghb[S + 1];  // source at input row - k
+    T sha[S + 2], shb[S + 2];  // coefficient at input row - k
     unsigned long long pr[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        w[s][0] = w[s][1] = w[s][2] = T(0);
+        wa[s][0] = wa[s][1] = wa[s][2] = wb[s][0] = wb[s][1] = wb[s][2] = T(0);
         pr[s] = 0;
     }
 #pragma unroll
-    for (int k = 0; k < S + 1; ++k) gh[k] = T(0);
+    for (int k = 0; k < S + 1; ++k) gha[k] = ghb[k] = T(0);
 #pragma unroll
-    for (int k = 0; k < S + 2; ++k) sh[k] = T(1);
+    for (int k = 0; k < S + 2; ++k) sha[k] = shb[k] = T(1);
 
     const int rows = (y1 - y0) + 2 * S;
-    // bit k of ymask: input row - k lies on a Dirichlet y face (computed once
-    // per row, shifted along the pipeline)
-    unsigned ymask = 0;
-    // one input row through the pipeline: the prolonged value enters
-    // relaxation 1, each relaxation's output row enters the next one
-    auto step_row = [&](const RowIn<T> &R, int t, auto hasg) {
+    unsigned ymask = 0;  // bit k: input row - k lies on a Dirichlet y face
+    auto step_row = [&](const RowIn2<T> &R, int t, auto hasg) {
         constexpr bool HASG = decltype(hasg)::value;
-        const int rho = y0 - S + t;  // input row, outside the grid: its image
+        const int rho = y0 - S + t;
         const int rm = mir(rho, m);
-        T val = PRO ? prolonged<T>(R, xm, rm) : R.st;
+        T va, vb;
+        if (PRO) {
+            prolonged2<T>(R, rm, va, vb);
+        } else {
+            va = R.sta;
+            vb = R.stb;
+        }
 #pragma unroll
-        for (int k = S; k > 0; --k) gh[k] = gh[k - 1];
-        gh[0] = R.g;
+        for (int k = S; k > 0; --k) {
+            gha[k] = gha[k - 1];
+            ghb[k] = ghb[k - 1];
+        }
+        gha[0] = R.ga;
+        ghb[0] = R.gb;
         ymask = (ymask << 1) | (unsigned)(((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1));
         if (SIG) {
 #pragma unroll
-            for (int k = S + 1; k > 0; --k) sh[k] = sh[k - 1];
-            sh[0] = R.sg;
+            for (int k = S + 1; k > 0; --k) {
+                sha[k] = sha[k - 1];
+                shb[k] = shb[k - 1];
+            }
+            sha[0] = R.sga;
+            shb[0] = R.sgb;
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            w[s][0] = w[s][1];
-            w[s][1] = w[s][2];
-            w[s][2] = val;
+            wa[s][0] = wa[s][1];
+            wa[s][1] = wa[s][2];
+            wa[s][2] = va;
+            wb[s][0] = wb[s][1];
+            wb[s][1] = wb[s][2];
+            wb[s][2] = vb;
             const int r = rho - s - 1;  // row relaxation s+1 produces now
-            const bool dir = xdir || ((ymask >> (s + 1)) & 1u);
-            T gval = T(0);
-            if (HASG && dir) gval = (T)ld(G, (unsigned)mir(r, m) * (unsigned)gpitch + (unsigned)glane);
-            const T sg[3] = {sh[s + 2], sh[s + 1], sh[s]};
-            T resid = T(0);
-            val = relax<T, RAD, SIG, REC>(w[s], sg, gh[s + 1], dir, gval, K, resid);
-            if (REC && A.pres[s] >= 0 && r >= y0 && r < y1 && xout) {
-                const unsigned long long b = dbits((double)resid);
+            const bool yd = (ymask >> (s + 1)) & 1u;
+            const bool da = xda || yd, db = xdb || yd;
+            T gva = T(0), gvb = T(0);
+            if (HASG) {
+                const unsigned grow = (unsigned)mir(r, m) * (unsigned)gpitch;
+                if (da) gva = (T)ld(G, grow + (unsigned)(xma * L.lam));
+                if (db) gvb = (T)ld(G, grow + (unsigned)(xmb * L.lam));
+            }
+            const T sga[3] = {sha[s + 2], sha[s + 1], sha[s]};
+            const T sgb[3] = {shb[s + 2], shb[s + 1], shb[s]};
+            T resa = T(0), resb = T(0);
+            relax2<T, RAD, SIG, REC>(wa[s], wb[s], sga, sgb, gha[s + 1], ghb[s + 1], da, db, gva, gvb, K, va, vb,
+                                     resa, resb);
+            if (REC && A.pres[s] >= 0 && r >= y0 && r < y1) {
+                unsigned long long b = 0;
+                if (outa) b = dbits((double)resa);
+                if (outb) {
+                    const unsigned long long bb = dbits((double)resb);
+                    b = bb > b ? bb : b;
+                }
                 pr[s] = b > pr[s] ? b : pr[s];
             }
         }
         const int ro = rho - S;
-        if (ro >= y0 && ro < y1 && xout) {
-            st(eout, (unsigned)ro * (unsigned)m + (unsigned)x, val);
-            if (inject && !(ro & 1) && !(x & 1))
-                st(einj, (unsigned)(ro >> 1) * (unsigned)((m + 1) >> 1) + (unsigned)(x >> 1), val);
+        if (ro >= y0 && ro < y1) {
+            const unsigned q = (unsigned)ro * (unsigned)m + (unsigned)xa;
+            if (outa) {
+                st(eout, q, va);
+                if (inject && !(ro & 1))
+                    st(einj, (unsigned)(ro >> 1) * (unsigned)((m + 1) >> 1) + (unsigned)(xa >> 1), va);
+            }
+            if (outb) st(eout, q + 1u, vb);
         }
     };
-    // raw loads in batches of B rows, one batch in flight while the other is
-    // consumed (the unrolled batches turn the window shifts into renames)
     constexpr int B = 3;
-    RowIn<T> qa[B], qb[B];
-    auto load_batch = [&](RowIn<T>(&q)[B], int t0) {
+    RowIn2<T> qa[B], qb[B];
+    auto load_batch = [&](RowIn2<T>(&q)[B], int t0) {
 #pragma unroll
         for (int k = 0; k < B; ++k)
-            if (t0 + k < rows) load_row<T, PRO, SIG>(q[k], A, xm, y0 - S + t0 + k, m);
+            if (t0 + k < rows) load_row2<T, PRO, SIG>(q[k], A, xma, xmb, y0 - S + t0 + k, m);
     };
-    // the first cycle carries Dirichlet values: one copy of the row loop each
     auto march = [&](auto hasg) {
         load_batch(qa, 0);
         for (int t0 = 0; t0 < rows; t0 += 2 * B) {
@@ -502,10 +567,10 @@ int chunk_rows(int requested, int m, int strips, int sweeps)
 template <typename T, int RAD, int SIG, int S, int PRO, int REC>
 void launch_one(const VisitArgs &a0, hipStream_t st)
 {
-    constexpr int W = 64 - 2 * (S + PRO);
     VisitArgs a = a0;
     const int m = a.L.m;
-    a.chunk = chunk_rows(a0.chunk, m, (m + W - 1) / W, S);
+    constexpr int W = 128 - 2 * ((S + PRO + 1) / 2 * 2);
+    a.chunk = chunk_rows(a0.chunk, m, 2 * ((m + W - 1) / W), S);
     const long long waves = (long long)((m + W - 1) / W) * ((m + a.chunk - 1) / a.chunk);
     const unsigned blocks = (unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64));
     hipLaunchKernelGGL((k_visit2d<T, RAD, SIG, S, PRO, REC>), dim3(blocks), dim3(kVisitBlock), 0, st, a);
@@ -539,7 +604,6 @@ void launch_rs(const VisitArgs &a, hipStream_t st)
 
 }  // namespace
 
-bool fused_visit_supported(int sweeps) { return sweeps == 1 || sweeps == 2 || sweeps == 4 || sweeps == 6; }
 
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st)
@@ -569,8 +633,6 @@ void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st
 #undef SGML_CE
 }
 
-template void launch_cycle_end2d<double>(const Variant &, const CycleEndArgs &, hipStream_t);
-template void launch_cycle_end2d<float>(const Variant &, const CycleEndArgs &, hipStream_t);
 
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st)
@@ -585,7 +647,5 @@ void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st)
         launch_rs<T, 0, 0>(a, st);
 }
 
-template void launch_visit2d<double>(const Variant &, const VisitArgs &, hipStream_t);
-template void launch_visit2d<float>(const Variant &, const VisitArgs &, hipStream_t);
 
 }  // namespace sgml

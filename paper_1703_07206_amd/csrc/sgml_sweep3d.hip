@@ -2,7 +2,7 @@
 //
 // A block owns a 64 x 8 tile of (x, y) columns and a chunk of z planes.
 // Each plane of the level's values (and of the coefficient) is staged once,
-// with a one-node halo, in a ring of three LDS planes; a node's 26 (radial)
+// with a one-node halo, in a ring of LDS planes; a node's 26 (radial)
 // or 6 (axis) neighbours are then read from LDS instead of from L1/L2, and
 // every value crosses the memory hierarchy about once.  Halo cells outside
 // the grid hold the image node, so Neumann faces need no special case.  With
@@ -18,20 +18,49 @@ namespace {
 constexpr int TX = 64, TY = 8, ZC = 16;  // tile and z chunk
 constexpr int kThreads = TX * TY;
 constexpr int PX = TX + 2, PY = TY + 2;  // staged plane with halo
+constexpr int NP = PX * PY;               // staged plane cells (660)
+static_assert(NP <= 2 * kThreads, "two staged cells per thread");
+constexpr int RING = 4;  // planes in LDS: z-1, z, z+1 being read, z+2 being written
 
 // theta / D: the hardware reciprocal in FP32 (the mixed mode's approximate
 // inner solver), a division in FP64.
 __device__ __forceinline__ float step_of3(float theta, float D) { return theta * __builtin_amdgcn_rcpf(D); }
 __device__ __forceinline__ double step_of3(double theta, double D) { return theta / D; }
 
+// The two cells of a staged plane that thread t fills (t and t + kThreads)
+// and their in-plane image offsets, the same for every plane.
+struct StageCells {
+    unsigned q[2];
+    int ly[2], lx[2];
+    bool two;
+};
+__device__ __forceinline__ StageCells stage_cells(int x0, int y0, int m)
+{
+    StageCells c;
+    for (int k = 0; k < 2; ++k) {
+        const int idx = (int)threadIdx.x + k * kThreads;
+        const int i = idx < NP ? idx : 0;
+        c.ly[k] = i / PX;
+        c.lx[k] = i - c.ly[k] * PX;
+        c.q[k] = (unsigned)mir(y0 - 1 + c.ly[k], m) * (unsigned)m + (unsigned)mir(x0 - 1 + c.lx[k], m);
+    }
+    c.two = (int)threadIdx.x + kThreads < NP;
+    return c;
+}
+
+// Each plane is staged once with a one-node halo (images outside the grid)
+// in a ring of four LDS planes; the loads of plane z+2 are issued into
+// registers before plane z is computed and stored to LDS after, so their
+// latency overlaps the computation, and one barrier per plane suffices (the
+// plane being written is never one being read).
 template <typename T, int RAD, int SIG>
 __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein, T *__restrict__ eout,
                                                       const T *__restrict__ g, const T *__restrict__ sig,
                                                       const double *__restrict__ G, Level L,
                                                       unsigned long long *__restrict__ pres)
 {
-    __shared__ T su[3][PY][PX];
-    __shared__ T ss[SIG ? 3 : 1][SIG ? PY : 1][SIG ? PX : 1];
+    __shared__ T su[RING][NP];
+    __shared__ T ss[SIG ? RING : 1][SIG ? NP : 1];
     const int m = L.m;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
@@ -39,14 +68,27 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m;
+    const unsigned cxy = (unsigned)(own ? y : 0) * (unsigned)m + (unsigned)(own ? x : 0);
+    const StageCells cells = stage_cells(x0, y0, m);
+    const int ctr = (ty + 1) * PX + tx + 1;  // this thread's node in a staged plane
 
-    auto stage = [&](int slot, int zz) {
-        const size_t zoff = (size_t)mir(zz, m) * plane;
-        for (int idx = threadIdx.x; idx < PX * PY; idx += kThreads) {
-            const int ly = idx / PX, lx = idx % PX;
-            const size_t q = zoff + (size_t)mir(y0 - 1 + ly, m) * m + mir(x0 - 1 + lx, m);
-            su[slot][ly][lx] = ein[q];
-            if (SIG) ss[slot][ly][lx] = sig[q];
+    T pe[2] = {T(0), T(0)}, ps[2] = {T(1), T(1)};
+    auto fetch = [&](int zz) {
+        const T *__restrict__ ez = ein + (size_t)mir(zz, m) * plane;
+        pe[0] = ez[cells.q[0]];
+        if (cells.two) pe[1] = ez[cells.q[1]];
+        if (SIG) {
+            const T *__restrict__ sz = sig + (size_t)mir(zz, m) * plane;
+            ps[0] = sz[cells.q[0]];
+            if (cells.two) ps[1] = sz[cells.q[1]];
+        }
+    };
+    auto put = [&](int slot) {
+        su[slot][threadIdx.x] = pe[0];
+        if (cells.two) su[slot][threadIdx.x + kThreads] = pe[1];
+        if (SIG) {
+            ss[slot][threadIdx.x] = ps[0];
+            if (cells.two) ss[slot][threadIdx.x + kThreads] = ps[1];
         }
     };
     const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
@@ -59,22 +101,31 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
     // 26 neighbours of the middle plane's node are classes of these sums
     T cc[3] = {T(0), T(0), T(0)}, cx[3] = {T(0), T(0), T(0)}, ck[3] = {T(0), T(0), T(0)};
     auto plane_sums = [&](int slot, int at) {
-        cc[at] = su[slot][ty + 1][tx + 1];
-        cx[at] = (su[slot][ty + 1][tx] + su[slot][ty + 1][tx + 2]) + (su[slot][ty][tx + 1] + su[slot][ty + 2][tx + 1]);
-        if (RAD)
-            ck[at] = (su[slot][ty][tx] + su[slot][ty][tx + 2]) + (su[slot][ty + 2][tx] + su[slot][ty + 2][tx + 2]);
+        const T *P = su[slot];
+        cc[at] = P[ctr];
+        cx[at] = (P[ctr - 1] + P[ctr + 1]) + (P[ctr - PX] + P[ctr + PX]);
+        if (RAD) ck[at] = (P[ctr - PX - 1] + P[ctr - PX + 1]) + (P[ctr + PX - 1] + P[ctr + PX + 1]);
     };
-    stage(0, z0 - 1);
-    stage(1, z0);
+    fetch(z0 - 1);
+    put(0);
+    fetch(z0);
+    put(1);
+    fetch(z0 + 1);
+    T gnext = own ? g[(size_t)z0 * plane + cxy] : T(0);
+    __syncthreads();
     if (!SIG) {
-        __syncthreads();
         plane_sums(0, 1);  // at = 1: plane z-1 of the first node, shifted in below
         plane_sums(1, 2);
     }
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
-        const int sm = k % 3, sc = (k + 1) % 3, sp = (k + 2) % 3;  // planes z-1, z, z+1
-        stage(sp, z + 1);
+        const int sm = k % RING, sc = (k + 1) % RING, sp = (k + 2) % RING;  // planes z-1, z, z+1
+        put(sp);  // plane z+1
+        const T gc = gnext;
+        if (z + 1 < z1) {  // the next plane's loads, in flight while this one is computed
+            fetch(z + 2);
+            if (own) gnext = g[(size_t)(z + 1) * plane + cxy];
+        }
         __syncthreads();
         if (!SIG) {
             cc[0] = cc[1], cc[1] = cc[2];
@@ -83,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
             plane_sums(sp, 2);  // cc/cx/ck[0..2]: planes z-1, z, z+1
         }
         if (own) {
-            const size_t c = (size_t)z * plane + (size_t)y * m + x;
+            const size_t c = (size_t)z * plane + cxy;
             if (is_dir<3>(x, y, z, m, L.dir)) {
                 eout[c] = G ? (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)] : T(0);
             } else if (!SIG) {
@@ -95,16 +146,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
                     const T corners = ck[0] + ck[2];
                     sum = faces + T(0.5) * edges + T(1.0 / 3.0) * corners;
                 }
-                const T r = scale * (sum - Wc * uc) + a * uc - g[c];
+                const T r = scale * (sum - Wc * uc) + a * uc - gc;
                 eout[c] = uc + tD * r;
                 if (pres) {
                     const unsigned long long b = dbits((double)r);
                     rb = b > rb ? b : rb;
                 }
             } else {
-                const int slots[3] = {sm, sc, sp};
-                const T uc = su[sc][ty + 1][tx + 1];
-                const T sgc = ss[sc][ty + 1][tx + 1];
+                const T *Pu[3] = {su[sm], su[sc], su[sp]};
+                const T *Ps[3] = {ss[sm], ss[sc], ss[sp]};
+                const T uc = Pu[1][ctr];
+                const T sgc = Ps[1][ctr];
                 T acc[3] = {T(0), T(0), T(0)}, ds[3] = {T(0), T(0), T(0)};
 #pragma unroll
                 for (int dz = -1; dz <= 1; ++dz) {
@@ -114,9 +166,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
                         for (int dx = -1; dx <= 1; ++dx) {
                             const int cls = (dx != 0) + (dy != 0) + (dz != 0);
                             if (cls == 0 || (!RAD && cls != 1)) continue;
-                            const int s = slots[dz + 1];
-                            const T du = su[s][ty + 1 + dy][tx + 1 + dx] - uc;
-                            const T t = ss[s][ty + 1 + dy][tx + 1 + dx] + sgc;
+                            const int o = ctr + dy * PX + dx;
+                            const T du = Pu[dz + 1][o] - uc;
+                            const T t = Ps[dz + 1][o] + sgc;
                             acc[cls - 1] += t * du;
                             ds[cls - 1] += t;
                         }
@@ -126,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
                 const T sw = acc[0] + T(0.5) * acc[1] + third * acc[2];
                 const T Lu = scale * T(0.5) * sw + a * uc;
                 const T D = scale * T(0.5) * (ds[0] + T(0.5) * ds[1] + third * ds[2]) - a;
-                const T r = Lu - g[c];
+                const T r = Lu - gc;
                 eout[c] = uc + step_of3(theta, D) * r;
                 if (pres) {
                     const unsigned long long b = dbits((double)r);
@@ -134,7 +186,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
                 }
             }
         }
-        __syncthreads();  // the next iteration overwrites plane z-1's slot
     }
     if (pres) {
 #pragma unroll
@@ -152,12 +203,14 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
 // End of a cycle on a 3D level 0 (recurrence of Sec. 2, FP64), marching in
 // z like k_sweep3d: e = escale * E with Dirichlet values replaced by G (first
 // cycle) or 0 is staged per plane in LDS, then u += e, s -= dL_1 e at
-// unknowns (s = 0 at Dirichlet nodes), shat = s * shat_scale, max |s|.
+// unknowns (s = 0 at Dirichlet nodes), shat = s * shat_scale, max |s|.  The
+// next plane's e, coefficient, s and u are loaded into registers while the
+// current plane is computed.
 template <typename T, int RAD, int SIG>
 __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
 {
-    __shared__ double se[3][PY][PX];
-    __shared__ double ss[SIG ? 3 : 1][SIG ? PY : 1][SIG ? PX : 1];
+    __shared__ double se[RING][NP];
+    __shared__ double ss[SIG ? RING : 1][SIG ? NP : 1];
     const Level L = A.L;
     const int m = L.m;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -166,42 +219,77 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m;
+    const unsigned cxy = (unsigned)(own ? y : 0) * (unsigned)m + (unsigned)(own ? x : 0);
+    const StageCells cells = stage_cells(x0, y0, m);
+    const int ctr = (ty + 1) * PX + tx + 1;
     const T *__restrict__ E = (const T *)A.e;
     const double *__restrict__ G = A.G;
     const double *__restrict__ sig = A.sigma;
     T *__restrict__ shat = (T *)A.shat;
+    // whether each staged cell lies on a Dirichlet x or y face (z: per plane)
+    bool dxy[2];
+    for (int k = 0; k < 2; ++k) {
+        const int xm = mir(x0 - 1 + cells.lx[k], m), ym = mir(y0 - 1 + cells.ly[k], m);
+        dxy[k] = is_dir<2>(xm, ym, 0, m, L.dir);
+    }
 
-    auto stage = [&](int slot, int zz) {
+    double pe[2] = {0.0, 0.0}, ps[2] = {1.0, 1.0};
+    double s_next = 0.0, u_next = 0.0;
+    auto fetch = [&](int zz) {
         const int zm = mir(zz, m);
         const size_t zoff = (size_t)zm * plane;
-        for (int idx = threadIdx.x; idx < PX * PY; idx += kThreads) {
-            const int ly = idx / PX, lx = idx % PX;
-            const int ym = mir(y0 - 1 + ly, m), xm = mir(x0 - 1 + lx, m);
-            const size_t q = zoff + (size_t)ym * m + xm;
+        const bool dz = ((L.dir & 16u) && zm == 0) || ((L.dir & 32u) && zm == m - 1);
+        for (int k = 0; k < 2; ++k) {
+            if (k == 1 && !cells.two) break;
+            const size_t q = zoff + cells.q[k];
             double v = A.escale * (double)E[q];
-            if (is_dir<3>(xm, ym, zm, m, L.dir)) v = G ? G[q] : 0.0;
-            se[slot][ly][lx] = v;
-            if (SIG) ss[slot][ly][lx] = sig[q];
+            if (dz || dxy[k]) v = G ? G[q] : 0.0;
+            pe[k] = v;
+            if (SIG) ps[k] = sig[q];
+        }
+    };
+    auto put = [&](int slot) {
+        se[slot][threadIdx.x] = pe[0];
+        if (cells.two) se[slot][threadIdx.x + kThreads] = pe[1];
+        if (SIG) {
+            ss[slot][threadIdx.x] = ps[0];
+            if (cells.two) ss[slot][threadIdx.x + kThreads] = ps[1];
         }
     };
     unsigned long long nb = 0;
-    stage(0, z0 - 1);
-    stage(1, z0);
+    fetch(z0 - 1);
+    put(0);
+    fetch(z0);
+    put(1);
+    fetch(z0 + 1);
+    if (own) {
+        s_next = A.s[(size_t)z0 * plane + cxy];
+        u_next = A.u[(size_t)z0 * plane + cxy];
+    }
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
-        const int sm = k % 3, sc = (k + 1) % 3, sp = (k + 2) % 3;
-        stage(sp, z + 1);
+        const int sm = k % RING, sc = (k + 1) % RING, sp = (k + 2) % RING;
+        put(sp);
+        const double s_c = s_next, u_c = u_next;
+        if (z + 1 < z1) {
+            fetch(z + 2);
+            if (own) {
+                s_next = A.s[(size_t)(z + 1) * plane + cxy];
+                u_next = A.u[(size_t)(z + 1) * plane + cxy];
+            }
+        }
         __syncthreads();
         if (own) {
-            const size_t c = (size_t)z * plane + (size_t)y * m + x;
-            const double ec = se[sc][ty + 1][tx + 1];
-            A.u[c] += ec;
+            const size_t c = (size_t)z * plane + cxy;
+            const double *Pe[3] = {se[sm], se[sc], se[sp]};
+            const double *Ps[3] = {ss[SIG ? sm : 0], ss[SIG ? sc : 0], ss[SIG ? sp : 0]};
+            const double ec = Pe[1][ctr];
+            A.u[c] = u_c + ec;
             if (is_dir<3>(x, y, z, m, L.dir)) {
                 A.s[c] = 0.0;
                 if (shat) shat[c] = T(0);
             } else {
-                const int slots[3] = {sm, sc, sp};
-                const double sgc = SIG ? ss[sc][ty + 1][tx + 1] : 1.0;
+                const double sgc = SIG ? Ps[1][ctr] : 1.0;
                 double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                 for (int dz = -1; dz <= 1; ++dz) {
@@ -211,10 +299,10 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
                         for (int dx = -1; dx <= 1; ++dx) {
                             const int cls = (dx != 0) + (dy != 0) + (dz != 0);
                             if (cls == 0 || (!RAD && cls != 1)) continue;
-                            const int sl = slots[dz + 1];
-                            const double du = se[sl][ty + 1 + dy][tx + 1 + dx] - ec;
+                            const int o = ctr + dy * PX + dx;
+                            const double du = Pe[dz + 1][o] - ec;
                             if (SIG)
-                                acc[cls - 1] += (ss[sl][ty + 1 + dy][tx + 1 + dx] + sgc) * du;
+                                acc[cls - 1] += (Ps[dz + 1][o] + sgc) * du;
                             else
                                 acc[cls - 1] += du;
                         }
@@ -222,14 +310,13 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
                 }
                 const double sw = acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2];
                 const double Le = (SIG ? 0.5 * L.scale * sw : L.scale * sw) + L.a * ec;
-                const double sn = A.s[c] - Le;
+                const double sn = s_c - Le;
                 A.s[c] = sn;
                 if (shat) shat[c] = (T)(sn * A.shat_scale);
                 const unsigned long long b = dbits(sn);
                 nb = b > nb ? b : nb;
             }
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

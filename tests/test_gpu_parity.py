@@ -267,3 +267,25 @@ def test_fused_visits_converged(case):
         u, st = gpu_solve(wl, prec, tol=tol, max_cycles=200, fuse=64)
         assert st["status"] == 0
         assert rel_inf(u, u_or) < 1e-12
+
+
+@pytest.mark.parametrize("case", [(2, 10, AXIS, "DDNN", False, 0.0, True), (2, 10, RADIAL, "NDDN", True, -0.2, True)],
+                         ids=["n10-axis-DDNN-one", "n10-rad-NDDN-sig"])
+def test_per_cycle_parity_1025(case):
+    # every 2D kernel of the default path at once: the row-marching visits of
+    # level 0, LDS-tiled visits of levels 1..3 (513^2..129^2), the coarse
+    # levels in LDS, and the cycle end (mixed: with the level-1 restriction)
+    dim, n, stencil, faces, hetero, a, with_G = case
+    wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1500 + n)
+    P = oracle_problem(wl)
+    u_or, info = P.solve(wl.f, G=wl.G, tol=0.0, max_cycles=2)
+    u, st = gpu_solve(wl, tol=0.0, max_cycles=2)
+    assert rel_inf(u, u_or) < 1e-12, rel_inf(u, u_or)
+    assert abs(st["relres"] - info["relres"]) <= 1e-10 * info["relres"]
+    um, stm = gpu_solve(wl, "mixed", tol=0.0, max_cycles=2)
+    assert rel_inf(um, u_or) < 1e-5, rel_inf(um, u_or)
+    # refined to the FP64 bar against the oracle's converged solution
+    u_or_c, _ = P.solve(wl.f, G=wl.G, tol=1e-13, max_cycles=60)
+    umc, stc = gpu_solve(wl, "mixed", tol=1e-13, max_cycles=60)
+    assert stc["status"] == 0
+    assert rel_inf(umc, u_or_c) < 1e-12, rel_inf(umc, u_or_c)

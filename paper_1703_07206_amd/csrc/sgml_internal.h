@@ -162,6 +162,10 @@ void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, con
 template <typename T>
 void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first,
                     hipStream_t st);
+// The same interpolation into a 3D level of m = 2 mc - 1 >= 33 nodes per
+// axis, marching in z with the pending variation staged in LDS.
+template <typename T>
+void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st);
 
 template <typename T>
 void launch_inject(int dim, int mc, const T *ef, T *ec, hipStream_t st);

@@ -658,8 +658,12 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             launch_restrict<T, T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
             break;
         case kOpProlong:
-            launch_prolong<T>(P->dim, (o.m + 1) / 2, (const T *)o.in0, (const T *)o.in1, (T *)o.out,
-                              o.first != 0, st);
+            if (P->dim == 3 && use_sweep3d && sweep3d_supported(o.m))
+                launch_prolong3d<T>((o.m + 1) / 2, (const T *)o.in0, (const T *)o.in1, (T *)o.out, o.first != 0,
+                                    st);
+            else
+                launch_prolong<T>(P->dim, (o.m + 1) / 2, (const T *)o.in0, (const T *)o.in1, (T *)o.out,
+                                  o.first != 0, st);
             break;
         case kOpInject:
             launch_inject<T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);

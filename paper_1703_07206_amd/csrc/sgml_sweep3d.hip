@@ -329,6 +329,74 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
     }
 }
 
+// Interpolation of the pending variation of level nu+1 into level nu (3D,
+// m >= 33), marching in z.  The pending variation at coarse node X is
+// p(X) = ec(X) - efin(2X) (efin = 0 on the level's first visit of a cycle);
+// every fine node takes efin + the trilinear interpolant of p, which at a
+// coarse node is ec itself.  A block owns 64 x 8 fine columns and 16 fine
+// planes: it stages p of the 33 x 5 coarse columns it needs, one coarse plane
+// at a time in a two-plane LDS ring, and streams efin -> efout.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec, const T *__restrict__ efin,
+                                                        T *__restrict__ efout, int mc, int first)
+{
+    constexpr int CXT = TX / 2 + 1, CYT = TY / 2 + 1;  // coarse columns of the tile
+    __shared__ T sp[2][CYT * CXT];
+    const int m = 2 * mc - 1;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;  // even
+    const int z1 = min(m, z0 + ZC);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < m && y < m;
+    const size_t plane = (size_t)m * m, cplane = (size_t)mc * mc;
+    const unsigned cxy = (unsigned)(own ? y : 0) * (unsigned)m + (unsigned)(own ? x : 0);
+    // the staged coarse cell of this thread (threads beyond CXT * CYT stage nothing)
+    const bool stager = threadIdx.x < CXT * CYT;
+    const int scy = threadIdx.x / CXT, scx = threadIdx.x - scy * CXT;
+    const int X = min(x0 / 2 + scx, mc - 1), Y = min(y0 / 2 + scy, mc - 1);
+    auto stage = [&](int slot, int Z) {
+        if (!stager) return;
+        Z = min(Z, mc - 1);
+        T v = ec[(size_t)Z * cplane + (size_t)Y * mc + X];
+        if (!first) v -= efin[(size_t)(2 * Z) * plane + (size_t)(2 * Y) * m + 2 * X];
+        sp[slot][threadIdx.x] = v;
+    };
+    const int oi = x & 1, oj = y & 1;
+    const int c00 = (ty >> 1) * CXT + (tx >> 1);  // coarse cell (X, Y) of this column in the tile
+    const T wxy = (oi && oj) ? T(0.25) : ((oi || oj) ? T(0.5) : T(1));
+    // the interpolant of p within one coarse plane at this column (x, y)
+    auto in_plane = [&](int slot) {
+        const T *P = sp[slot];
+        T acc = P[c00];
+        if (oi) acc += P[c00 + 1];
+        if (oj) acc += P[c00 + CXT];
+        if (oi && oj) acc += P[c00 + CXT + 1];
+        return acc;
+    };
+    int Zs = z0 / 2;  // coarse plane in slot Zs & 1
+    stage(Zs & 1, Zs);
+    stage((Zs + 1) & 1, Zs + 1);
+    __syncthreads();
+    T stale_next = (own && !first) ? efin[(size_t)z0 * plane + cxy] : T(0);
+    for (int z = z0; z < z1; ++z) {
+        const int Z = z >> 1, ok = z & 1;
+        if (Z + 1 > Zs + 1) {  // move the ring on: coarse plane Z + 1 replaces Z - 1
+            __syncthreads();  // every thread is done with the plane being replaced
+            stage((Z + 1) & 1, Z + 1);
+            Zs = Z;
+            __syncthreads();
+        }
+        const T stale = stale_next;
+        if (z + 1 < z1 && own && !first) stale_next = efin[(size_t)(z + 1) * plane + cxy];
+        if (own) {
+            T acc = in_plane(Z & 1);
+            if (ok) acc += in_plane((Z + 1) & 1);
+            const T w = ok ? T(0.5) * wxy : wxy;
+            efout[(size_t)z * plane + cxy] = stale + w * acc;
+        }
+    }
+}
+
 }  // namespace
 
 bool sweep3d_supported(int m) { return m >= 33; }
@@ -366,6 +434,17 @@ void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, con
     else
         hipLaunchKernelGGL((k_sweep3d<T, 0, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres);
 }
+
+template <typename T>
+void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)
+{
+    const int m = 2 * mc - 1;
+    const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + ZC - 1) / ZC), block(kThreads);
+    hipLaunchKernelGGL((k_prolong3d<T>), grid, block, 0, st, ec, ef_in, ef_out, mc, (int)first);
+}
+
+template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, hipStream_t);
+template void launch_prolong3d<float>(int, const float *, const float *, float *, bool, hipStream_t);
 
 template void launch_sweep3d<double>(const Variant &, const Level &, const double *, double *, const double *,
                                      const double *, const double *, unsigned long long *, hipStream_t);

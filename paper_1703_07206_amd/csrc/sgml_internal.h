@@ -172,6 +172,9 @@ void launch_inject(int dim, int mc, const T *ef, T *ec, hipStream_t st);
 
 template <typename Tin, typename Tout>
 void launch_restrict(int dim, int mc, const Tin *fine, Tout *coarse, hipStream_t st);
+// The same step from a 3D level of 2 mc - 1 >= 33 nodes per axis, marching in z.
+template <typename T>
+void launch_restrict3d(int mc, const T *fine, T *coarse, hipStream_t st);
 
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, size_t count, hipStream_t st);

@@ -655,7 +655,10 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             launch_fill<T>((T *)o.out, level_nodes(P->dim, P->n, o.level), T(0), st);
             break;
         case kOpRestrict:
-            launch_restrict<T, T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
+            if (P->dim == 3 && use_sweep3d && sweep3d_supported(2 * o.m - 1))
+                launch_restrict3d<T>(o.m, (const T *)o.in0, (T *)o.out, st);
+            else
+                launch_restrict<T, T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
             break;
         case kOpProlong:
             if (P->dim == 3 && use_sweep3d && sweep3d_supported(o.m))

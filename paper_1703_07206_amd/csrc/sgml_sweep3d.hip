@@ -397,6 +397,88 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
     }
 }
 
+// One restriction step (Algorithm 1, eq. (4)) from a 3D level of mf >= 33
+// nodes per axis, marching in z.  Coarse node X averages the fine 3^3 block
+// around 2X with weights hat(p/2) per axis over 8; images outside the grid.
+// A block owns 64 x 8 coarse columns; each fine plane is staged once (a
+// 129 x 17 region, two planes in flight, the next one loaded into registers
+// while the current is summed); each thread forms its column's in-plane
+// weighted sum h(zf) and combines h(2Z-1), h(2Z), h(2Z+1) with (1/2, 1, 1/2).
+constexpr int RCX = 64, RCY = 8;                                   // coarse tile
+constexpr int RFX = 2 * RCX + 1, RFY = 2 * RCY + 1, RNP = RFX * RFY;  // staged fine plane
+constexpr int RLI = (RNP + kThreads - 1) / kThreads;               // staged cells per thread
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict3d(const T *__restrict__ fine, T *__restrict__ coarse, int mc)
+{
+    __shared__ T sf[2][RNP];
+    const int mf = 2 * mc - 1;
+    const int tx = threadIdx.x % RCX, ty = threadIdx.x / RCX;
+    const int X0 = blockIdx.x * RCX, Y0 = blockIdx.y * RCY, Z0 = blockIdx.z * ZC;
+    const int Z1 = min(mc, Z0 + ZC);
+    const int X = X0 + tx, Y = Y0 + ty;
+    const bool own = X < mc && Y < mc;
+    const size_t fplane = (size_t)mf * mf;
+    // in-plane image offsets of this thread's staged cells (fine columns
+    // 2 X0 - 1 .. 2 X0 + 2 RCX - 1); the nodes of coarse columns in range need
+    // at most one reflection, the rest (past the grid, for small levels) are
+    // clamped into it and never used
+    auto img = [&](int c) { return min(max(mir(c, mf), 0), mf - 1); };
+    unsigned q[RLI];
+#pragma unroll
+    for (int k = 0; k < RLI; ++k) {
+        const int idx = (int)threadIdx.x + k * kThreads;
+        const int i = idx < RNP ? idx : 0;
+        const int ly = i / RFX, lx = i - ly * RFX;
+        q[k] = (unsigned)img(2 * Y0 - 1 + ly) * (unsigned)mf + (unsigned)img(2 * X0 - 1 + lx);
+    }
+    T pf[RLI];
+    auto fetch = [&](int zf) {
+        const T *__restrict__ pz = fine + (size_t)img(zf) * fplane;
+#pragma unroll
+        for (int k = 0; k < RLI; ++k)
+            if ((int)threadIdx.x + k * kThreads < RNP) pf[k] = pz[q[k]];
+    };
+    auto put = [&](int slot) {
+#pragma unroll
+        for (int k = 0; k < RLI; ++k)
+            if ((int)threadIdx.x + k * kThreads < RNP) sf[slot][threadIdx.x + k * kThreads] = pf[k];
+    };
+    const int c = (2 * ty + 1) * RFX + 2 * tx + 1;  // fine node 2X, 2Y in the staged plane
+    auto hsum = [&](int slot) {
+        const T *P = sf[slot];
+        const T r0 = T(0.5) * P[c - RFX - 1] + P[c - RFX] + T(0.5) * P[c - RFX + 1];
+        const T r1 = T(0.5) * P[c - 1] + P[c] + T(0.5) * P[c + 1];
+        const T r2 = T(0.5) * P[c + RFX - 1] + P[c + RFX] + T(0.5) * P[c + RFX + 1];
+        return T(0.5) * r0 + r1 + T(0.5) * r2;
+    };
+    // fine planes 2 Z0 - 1 .. 2 Z1 - 1
+    const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
+    fetch(zf0);
+    put(0);
+    fetch(zf0 + 1);
+    T hm = T(0), hc = T(0);  // h(2Z - 1), h(2Z)
+    for (int zf = zf0; zf <= zf1; ++zf) {
+        const int k = zf - zf0;
+        __syncthreads();  // plane zf is in slot k & 1; the other slot is free
+        if (zf < zf1) {
+            put((k + 1) & 1);  // plane zf + 1 (loaded last iteration)
+            if (zf + 2 <= zf1) fetch(zf + 2);
+        }
+        const T h = hsum(k & 1);
+        if (k == 0) {
+            hm = h;
+        } else if (k & 1) {
+            hc = h;
+        } else {
+            // zf = 2Z + 1: coarse plane Z complete
+            const int Z = (zf - 1) / 2;
+            if (own) coarse[((size_t)Z * mc + Y) * mc + X] = (T(0.5) * hm + hc + T(0.5) * h) * T(0.125);
+            hm = h;
+        }
+    }
+}
+
 }  // namespace
 
 bool sweep3d_supported(int m) { return m >= 33; }
@@ -445,6 +527,16 @@ void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first
 
 template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, hipStream_t);
 template void launch_prolong3d<float>(int, const float *, const float *, float *, bool, hipStream_t);
+
+template <typename T>
+void launch_restrict3d(int mc, const T *fine, T *coarse, hipStream_t st)
+{
+    const dim3 grid((mc + RCX - 1) / RCX, (mc + RCY - 1) / RCY, (mc + ZC - 1) / ZC), block(kThreads);
+    hipLaunchKernelGGL((k_restrict3d<T>), grid, block, 0, st, fine, coarse, mc);
+}
+
+template void launch_restrict3d<double>(int, const double *, double *, hipStream_t);
+template void launch_restrict3d<float>(int, const float *, float *, hipStream_t);
 
 template void launch_sweep3d<double>(const Variant &, const Level &, const double *, double *, const double *,
                                      const double *, const double *, unsigned long long *, hipStream_t);

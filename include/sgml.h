@@ -93,22 +93,25 @@ typedef struct {
     int schedule;     /* SGML_SCHEDULE_ONCE or SGML_SCHEDULE_EACH */
     int precision;    /* SGML_FP64 or SGML_MIXED; must not exceed the plan's */
     int record_pres;  /* 1: keep the per-visit pseudo-residuals of the last cycle */
-    int profile;      /* 1: time every level-0 sweep and boundary pass with stream
-                         events (sweep0_ms, boundary_ms in the stats) */
+    int profile;      /* 1: time every level-0 launch (fused visit, relaxation,
+                         cycle-end pass) with stream events (prof_* in the stats) */
     int coarse_nodes; /* levels of at most this many nodes run together in one
-                         single-workgroup launch per run of coarse operations;
+                         single-workgroup launch per run of coarse operations
+                         (their arrays staged in LDS when they fit);
                          0: default (5000), < 0: every operation launched alone */
     int stall_window; /* SGML_E_STAGNATED when the residual has not halved over
                          this many cycles; 0: default (3), < 0: never */
     int fuse;         /* 2D levels with at least this many nodes per axis (and
                          too large for the coarse kernel) run each visit as one
-                         fused pass; 0: default (1025), < 0: never (one launch per
-                         interpolation, relaxation and injection, and the
-                         generic relaxation and cycle-end kernels in 2D and 3D);
-                         values below 64 act as 64 */
-    int chunk_rows;   /* rows each wavefront marches through in the 2D fused passes;
-                         0: chosen per launch (16, or 32 for long fused visits of
-                         large levels), values below 8 act as 8 */
+                         fused pass (LDS tiles up to 1025 nodes per axis,
+                         row-marching above); 0: default (129), < 0: never (one
+                         launch per interpolation, relaxation and injection, and
+                         the generic relaxation, transfer and cycle-end kernels in
+                         2D and 3D); values below 64 act as 64 */
+    int chunk_rows;   /* rows each wavefront marches through in the 2D row-marching
+                         passes; 0: chosen per launch (8 for short visits, 48 / 96
+                         (FP32 / FP64) for long visits of large levels, 96 for the
+                         cycle end), values below 8 act as 8 */
 } sgml_opts;
 
 #define SGML_HIST 512

@@ -158,6 +158,11 @@ void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
 template <typename T>
 void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
                     const double *G, unsigned long long *pres, hipStream_t st);
+// Two chained relaxations of a 3D level with sigma = 1 (m >= 33) in one
+// z-marching pass: ein -> (relaxation) -> (relaxation) -> eout.
+template <typename T>
+void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const double *G,
+                     unsigned long long *pres, hipStream_t st);
 
 template <typename T>
 void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first,

@@ -250,7 +250,8 @@ struct Timed {
 };
 
 // A cycle compiled to a list of operations (the same list every cycle).
-constexpr int kOpVisit = 5;  // fused visit of a 2D level (host-side operation)
+constexpr int kOpVisit = 5;   // fused visit of a 2D level (host-side operation)
+constexpr int kOpSweep2 = 6;  // two relaxations of a 3D level in one pass (host-side operation)
 
 struct HostOp {
     CoarseOp op;
@@ -297,6 +298,9 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
     // visits of large 2D levels run as fused passes
     auto fusable = [&](int nu) {
         return fuse_min > 0 && P->dim == 2 && nu < coarse_level && P->m(nu) >= fuse_min;
+    };
+    auto pairable3d = [&](int nu) {
+        return fuse_min > 0 && P->dim == 3 && nu < coarse_level && sweep3d_supported(P->m(nu)) && !P->var.sigma;
     };
     for (int nu = 1; nu < n; ++nu) {
         E[nu][0] = P->at<T>(P->lay.e[nu][0]);
@@ -347,10 +351,14 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
         updates_per_cycle += (long long)cnt[v] * (long long)level_nodes(P->dim, n, nu);
         const int tgt_last = record ? kPres + (int)v : -1;
         if (!fusable(nu)) {
-            for (int r = 0; r < cnt[v]; ++r) {
-                push(kOpSweep, nu, 0, r == cnt[v] - 1 ? tgt_last : -1, E[nu][cur[nu]], g[nu], sig[nu],
-                     E[nu][cur[nu] ^ 1], nu >= coarse_level);
+            for (int r = 0; r < cnt[v];) {
+                // pairs of relaxations of a large 3D level in one pass (sigma = 1);
+                // the pass writes the other buffer, as one relaxation does
+                const bool pair = pairable3d(nu) && r + 1 < cnt[v];
+                push(pair ? kOpSweep2 : kOpSweep, nu, 0, r + (pair ? 1 : 0) == cnt[v] - 1 ? tgt_last : -1,
+                     E[nu][cur[nu]], g[nu], sig[nu], E[nu][cur[nu] ^ 1], nu >= coarse_level);
                 cur[nu] ^= 1;
+                r += pair ? 2 : 1;
             }
             prev = nu;
             continue;
@@ -434,6 +442,7 @@ int op_refs(const sgml_plan *P, const HostOp &h, Ref r[6])
         ref(o.out, o.level, true);
         break;
     case kOpSweep:
+    case kOpSweep2:
         ref(o.in0, o.level, false);
         ref(o.in1, o.level, false);
         ref(o.out, o.level, true);
@@ -654,6 +663,17 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
         case kOpFill:
             launch_fill<T>((T *)o.out, level_nodes(P->dim, P->n, o.level), T(0), st);
             break;
+        case kOpSweep2: {
+            hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
+            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            launch_sweep3d2<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1, G,
+                               o.target >= 0 ? target(P, o.target) : nullptr, st);
+            if (ev) {
+                SGML_HIP(hipEventRecord(ev[1], st));
+                timed.push_back({SGML_PROF_SWEEP0, 2, ev});
+            }
+            break;
+        }
         case kOpRestrict:
             if (P->dim == 3 && use_sweep3d && sweep3d_supported(2 * o.m - 1))
                 launch_restrict3d<T>(o.m, (const T *)o.in0, (T *)o.out, st);

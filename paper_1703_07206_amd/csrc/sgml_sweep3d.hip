@@ -329,6 +329,170 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
     }
 }
 
+// Two relaxations of a 3D level (sigma = 1) in one pass, marching in z:
+// relaxation 1 runs on the tile plus a one-node halo of every plane as soon
+// as the input planes below and above it are staged, relaxation 2 on the
+// tile itself one plane behind, reading relaxation 1's planes from a second
+// LDS ring; the level is read and written once for both.  Neighbour sums by
+// class (centre, in-plane faces, in-plane corners) are formed once per plane
+// and cell and kept in registers, as in k_sweep3d.
+constexpr int TY2 = 8, ZC2 = 32, kThreads2 = TX * TY2;  // tile, z chunk and block of the paired pass
+constexpr int IX = TX + 4, IY = TY2 + 4, NI = IX * IY;    // input plane, halo 2 (68 x 12)
+constexpr int SX = TX + 2, SY = TY2 + 2, NS = SX * SY;    // relaxation-1 plane, halo 1 (66 x 10)
+static_assert(NI <= 2 * kThreads2 && NS <= 2 * kThreads2, "two cells per thread");
+
+template <typename T, int RAD>
+__global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ein, T *__restrict__ eout,
+                                                       const T *__restrict__ g, const double *__restrict__ G,
+                                                       Level L, unsigned long long *__restrict__ pres)
+{
+    __shared__ T sin_[RING][NI];  // input planes
+    __shared__ T sgs[RING][NS];   // source on the relaxation-1 region
+    __shared__ T s1[RING][NS];    // relaxation-1 planes
+    const int m = L.m;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;  // TX x TY2 threads
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY2, z0 = blockIdx.z * ZC2;
+    const int z1 = min(m, z0 + ZC2);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < m && y < m;
+    const size_t plane = (size_t)m * m;
+    const unsigned lam = (unsigned)L.lam, Nf = (unsigned)L.N;
+
+    // input cells staged by this thread (tid, tid + kThreads2), image offsets;
+    // the cells an owned node depends on lie within one reflection (x <= m + 1),
+    // those past it (small levels) are clamped into the grid and never used
+    auto img = [&](int c) { return min(max(mir(c, m), 0), m - 1); };
+    unsigned qi[2];
+    const bool two_i = tid + kThreads2 < NI;
+    for (int k = 0; k < 2; ++k) {
+        const int idx = k == 0 ? tid : (two_i ? tid + kThreads2 : 0);
+        const int ly = idx / IX, lx = idx - ly * IX;
+        qi[k] = (unsigned)img(y0 - 2 + ly) * (unsigned)m + (unsigned)img(x0 - 2 + lx);
+    }
+    // relaxation-1 cells of this thread: position in the input and stage planes,
+    // image offsets, x/y Dirichlet faces, offset of their Dirichlet value in G
+    const bool two_s = tid + kThreads2 < NS;
+    int sidx[2], sin_c[2];
+    unsigned qs[2], gxy[2];
+    bool sdxy[2];
+    for (int k = 0; k < 2; ++k) {
+        const int idx = k == 0 ? tid : (two_s ? tid + kThreads2 : 0);
+        const int ly = idx / SX, lx = idx - ly * SX;
+        sidx[k] = idx;
+        sin_c[k] = (ly + 1) * IX + lx + 1;
+        const int xm = img(x0 - 1 + lx), ym = img(y0 - 1 + ly);
+        qs[k] = (unsigned)ym * (unsigned)m + (unsigned)xm;
+        gxy[k] = (unsigned)ym * lam * Nf + (unsigned)xm * lam;
+        sdxy[k] = is_dir<2>(xm, ym, 0, m, L.dir);
+    }
+    const int c2 = (ty + 1) * SX + tx + 1;  // own node in a relaxation-1 plane
+
+    const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
+    const T Wc = RAD ? T(6) + T(0.5) * T(12) + T(1.0 / 3.0) * T(8) : T(6);
+    const T tD = theta / (scale * Wc - a);
+    auto relax = [&](const T (&cc)[3], const T (&cx)[3], const T (&ck)[3], T gv, T &r) {
+        const T uc = cc[1];
+        const T faces = cx[1] + (cc[0] + cc[2]);
+        T sum = faces;
+        if (RAD) {
+            const T edges = ck[1] + (cx[0] + cx[2]);
+            const T corners = ck[0] + ck[2];
+            sum = faces + T(0.5) * edges + T(1.0 / 3.0) * corners;
+        }
+        r = scale * (sum - Wc * uc) + a * uc - gv;
+        return uc + tD * r;
+    };
+    auto sums = [&](const T *P, int c, int pitch, T &cc, T &cx, T &ck) {
+        cc = P[c];
+        cx = (P[c - 1] + P[c + 1]) + (P[c - pitch] + P[c + pitch]);
+        if (RAD) ck = (P[c - pitch - 1] + P[c - pitch + 1]) + (P[c + pitch - 1] + P[c + pitch + 1]);
+    };
+
+    // prefetched input plane (e at the staged cells, g at the relaxation-1 cells)
+    T pe[2] = {T(0), T(0)}, pg[2] = {T(0), T(0)};
+    auto fetch = [&](int zz) {
+        const size_t zo = (size_t)mir(zz, m) * plane;
+        pe[0] = ein[zo + qi[0]];
+        if (two_i) pe[1] = ein[zo + qi[1]];
+        pg[0] = g[zo + qs[0]];
+        if (two_s) pg[1] = g[zo + qs[1]];
+    };
+    auto put = [&](int slot) {
+        sin_[slot][tid] = pe[0];
+        if (two_i) sin_[slot][tid + kThreads2] = pe[1];
+        sgs[slot][sidx[0]] = pg[0];
+        if (two_s) sgs[slot][sidx[1]] = pg[1];
+    };
+    T a_cc[2][3] = {}, a_cx[2][3] = {}, a_ck[2][3] = {};  // input planes zs-1, zs, zs+1 at the relaxation-1 cells
+    T b_cc[3] = {}, b_cx[3] = {}, b_ck[3] = {};           // relaxation-1 planes z-1, z, z+1 at the own node
+    unsigned long long rb = 0;
+
+    fetch(z0 - 2);
+    for (int zi = z0 - 2; zi <= z1 + 1; ++zi) {
+        const int slot = (zi + 8) & 3;
+        put(slot);
+        if (zi + 1 <= z1 + 1) fetch(zi + 1);
+        __syncthreads();
+        // relaxation 1 on plane zs = zi - 1
+        const int zs = zi - 1;
+        for (int k = 0; k < 2; ++k) {
+            if (k == 1 && !two_s) break;
+            a_cc[k][0] = a_cc[k][1], a_cc[k][1] = a_cc[k][2];
+            a_cx[k][0] = a_cx[k][1], a_cx[k][1] = a_cx[k][2];
+            a_ck[k][0] = a_ck[k][1], a_ck[k][1] = a_ck[k][2];
+            sums(sin_[slot], sin_c[k], IX, a_cc[k][2], a_cx[k][2], a_ck[k][2]);
+        }
+        if (zs >= z0 - 1) {
+            const int zsm = mir(zs, m);
+            const bool zd = ((L.dir & 16u) && zsm == 0) || ((L.dir & 32u) && zsm == m - 1);
+            const int ss = (zs + 8) & 3;
+            for (int k = 0; k < 2; ++k) {
+                if (k == 1 && !two_s) break;
+                T r, v;
+                if (zd || sdxy[k])
+                    v = G ? (T)G[(size_t)zsm * lam * Nf * Nf + gxy[k]] : T(0);
+                else
+                    v = relax(a_cc[k], a_cx[k], a_ck[k], sgs[ss][sidx[k]], r);
+                s1[ss][sidx[k]] = v;
+            }
+        }
+        __syncthreads();
+        // relaxation 2 on plane z = zs - 1
+        if (zs >= z0 - 1) {
+            b_cc[0] = b_cc[1], b_cc[1] = b_cc[2];
+            b_cx[0] = b_cx[1], b_cx[1] = b_cx[2];
+            b_ck[0] = b_ck[1], b_ck[1] = b_ck[2];
+            sums(s1[(zs + 8) & 3], c2, SX, b_cc[2], b_cx[2], b_ck[2]);
+        }
+        const int z = zs - 1;
+        if (z >= z0 && z < z1 && own) {
+            const size_t c = (size_t)z * plane + (size_t)y * m + x;
+            if (is_dir<3>(x, y, z, m, L.dir)) {
+                eout[c] = G ? (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)] : T(0);
+            } else {
+                T r;
+                eout[c] = relax(b_cc, b_cx, b_ck, sgs[(z + 8) & 3][c2], r);
+                if (pres) {
+                    const unsigned long long b = dbits((double)r);
+                    rb = b > rb ? b : rb;
+                }
+            }
+        }
+    }
+    if (pres) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(rb, off, 64);
+            rb = o > rb ? o : rb;
+        }
+        if ((threadIdx.x & 63) == 0 && rb) {
+            const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z) + threadIdx.x / 64;
+            atomicMax(pres + (b % kRedSlots) * kRedStride, rb);
+        }
+    }
+}
+
 // Interpolation of the pending variation of level nu+1 into level nu (3D,
 // m >= 33), marching in z.  The pending variation at coarse node X is
 // p(X) = ec(X) - efin(2X) (efin = 0 on the level's first visit of a cycle);
@@ -516,6 +680,23 @@ void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, con
     else
         hipLaunchKernelGGL((k_sweep3d<T, 0, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres);
 }
+
+template <typename T>
+void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const double *G,
+                     unsigned long long *pres, hipStream_t st)
+{
+    const int m = L.m;
+    const dim3 grid((m + TX - 1) / TX, (m + TY2 - 1) / TY2, (m + ZC2 - 1) / ZC2), block(kThreads2);
+    if (v.radial)
+        hipLaunchKernelGGL((k_sweep3d2<T, 1>), grid, block, 0, st, ein, eout, g, G, L, pres);
+    else
+        hipLaunchKernelGGL((k_sweep3d2<T, 0>), grid, block, 0, st, ein, eout, g, G, L, pres);
+}
+
+template void launch_sweep3d2<double>(const Variant &, const Level &, const double *, double *, const double *,
+                                      const double *, unsigned long long *, hipStream_t);
+template void launch_sweep3d2<float>(const Variant &, const Level &, const float *, float *, const float *,
+                                     const double *, unsigned long long *, hipStream_t);
 
 template <typename T>
 void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)

@@ -61,6 +61,8 @@ CASES = [
     (3, 5, AXIS, "DDDDDD", True, -0.2, False),
     (3, 4, AXIS, "NDNDDN", True, -0.1, True),
     (3, 6, RADIAL, "DDDDDD", True, -0.5, True),
+    (3, 6, RADIAL, "DNDDND", False, -0.3, True),
+    (3, 6, AXIS, "NDNDDD", False, 0.0, True),
 ]
 IDS = [f"{d}d-n{n}-{'rad' if s else 'axis'}-{fc}-{'sig' if h else 'one'}" for d, n, s, fc, h, a, g in CASES]
 
@@ -79,7 +81,7 @@ def test_per_cycle_parity_fp64(case):
         assert abs(st["norm0"] - info["norm0"]) <= 1e-13 * info["norm0"]
 
 
-@pytest.mark.parametrize("case", CASES[:4] + CASES[6:8], ids=IDS[:4] + IDS[6:8])
+@pytest.mark.parametrize("case", CASES[:4] + CASES[6:8] + CASES[11:13], ids=IDS[:4] + IDS[6:8] + IDS[11:13])
 def test_pseudo_residuals_per_visit(case):
     dim, n, stencil, faces, hetero, a, with_G = case
     wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=200 + n)
@@ -102,8 +104,8 @@ def test_converged_parity_fp64(case):
     assert rel_inf(u_gpu, u_or) < 1e-12
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6], CASES[7], CASES[10]],
-                         ids=[IDS[1], IDS[2], IDS[6], IDS[7], IDS[10]])
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6], CASES[7], CASES[10], CASES[11]],
+                         ids=[IDS[1], IDS[2], IDS[6], IDS[7], IDS[10], IDS[11]])
 def test_mixed_precision(case):
     dim, n, stencil, faces, hetero, a, with_G = case
     wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=400 + n)

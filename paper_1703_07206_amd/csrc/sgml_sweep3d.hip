@@ -11,6 +11,8 @@
 // node instead of 26.
 #include "sgml_device.h"
 
+#include <type_traits>
+
 namespace sgml {
 
 namespace {
@@ -331,73 +333,174 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
 
 // Two relaxations of a 3D level (sigma = 1) in one pass, marching in z:
 // relaxation 1 runs on the tile plus a one-node halo of every plane as soon
-// as the input planes below and above it are staged, relaxation 2 on the
-// tile itself one plane behind, reading relaxation 1's planes from a second
-// LDS ring; the level is read and written once for both.  Neighbour sums by
-// class (centre, in-plane faces, in-plane corners) are formed once per plane
-// and cell and kept in registers, as in k_sweep3d.
-constexpr int TY2 = 8, ZC2 = 32, kThreads2 = TX * TY2;  // tile, z chunk and block of the paired pass
-constexpr int IX = TX + 4, IY = TY2 + 4, NI = IX * IY;    // input plane, halo 2 (68 x 12)
-constexpr int SX = TX + 2, SY = TY2 + 2, NS = SX * SY;    // relaxation-1 plane, halo 1 (66 x 10)
-static_assert(NI <= 2 * kThreads2 && NS <= 2 * kThreads2, "two cells per thread");
+// as the input planes below and above it are in LDS, relaxation 2 on the tile
+// itself one plane behind, from relaxation 1's plane; the level is read and
+// written once for both.  Neighbour sums by class (centre, in-plane faces,
+// in-plane corners) are formed once per plane and cell and kept in registers,
+// as in k_sweep3d.
+//
+// The input planes (values on the tile plus a two-node halo, source on the
+// relaxation-1 region) travel from global memory straight into a ring of
+// LDS slots (direct-to-LDS loads, no registers), kDepth planes ahead of the
+// plane being relaxed, so that a block keeps several planes of loads in
+// flight.  Every wavefront issues the same number of those loads per plane
+// (the slots are padded to two loads per thread), which makes the number of
+// loads still outstanding when a plane is needed a constant: the wait before
+// the barrier names it.
+//
+// Tiles are balanced: the tile width is m / ceil(m / 64) rounded up (57 at
+// m = 513 rather than eight tiles of 64 and one of a single column), and so
+// are the z chunks.  Consecutive tiles in (x, y, z) order go to one XCD
+// (dispatch deals blocks to the XCDs in turn), so that the halo rows two
+// neighbouring tiles share are read through the same L2.
+constexpr int TY2 = 8, ZC2 = 32, kThreads2 = TX * TY2;  // tile rows, z chunk (at most) and block
+constexpr int IXM = TX + 4, IY = TY2 + 4;               // input plane, halo 2 (at most 68 x 12)
+constexpr int SXM = TX + 2, SY = TY2 + 2;               // relaxation-1 plane, halo 1 (at most 66 x 10)
+constexpr int kSlotCells = 2 * kThreads2;               // 1024 cells per staged array of a slot
+static_assert(IXM * IY <= kSlotCells && SXM * SY <= kSlotCells, "two staged cells per thread");
+constexpr int kXcds = 8;
+
+// s_waitcnt: at most VM vector-memory and LGKM LDS operations of this
+// wavefront still outstanding (expcnt not waited for).
+template <int VM, int LGKM>
+__device__ __forceinline__ void wait_counts()
+{
+    static_assert(VM >= 0 && VM < 64 && LGKM >= 0 && LGKM < 16, "counter range");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (LGKM << 8));
+}
+
+// Workgroup barrier for LDS traffic: the wavefront's own LDS writes are done
+// and at most VM of its direct-to-LDS loads are outstanding; the compiler may
+// not move memory accesses across it.
+template <int VM>
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    wait_counts<VM, 0>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Direct-to-LDS load in the scalar-base form: lane i reads base + off (off
+// per lane, 32 bits) and writes LDS byte address lds + 4 i.
+__device__ __forceinline__ void lds_load_word_s(const void *base, unsigned off, unsigned lds)
+{
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1" ::"v"(off), "s"(base), "s"(lds)
+                 : "memory", "m0");
+}
+
+// Running max of |r| as the bit pattern the stop test uses (order-independent,
+// NaN above +inf): in FP32 the max of the float bits, widened at the end
+// (the widening is monotone), in FP64 the bits themselves.
+__device__ __forceinline__ unsigned res_bits(float r) { return __float_as_uint(r) & 0x7fffffffu; }
+__device__ __forceinline__ unsigned long long res_bits(double r) { return dbits(r); }
+__device__ __forceinline__ unsigned long long res_widen(unsigned b) { return dbits((double)__uint_as_float(b)); }
+__device__ __forceinline__ unsigned long long res_widen(unsigned long long b) { return b; }
+
+// The ring holds NSLOT planes (values on the tile plus halo 2, source on the
+// relaxation-1 region): plane i + 2 is staged while plane i is relaxed, into
+// the slot of plane i - 1.  With three slots and three-plane register windows,
+// the march is unrolled by three so that slots and windows are fixed per copy.
+constexpr int NSLOT = 3, kAhead = NSLOT - 1;
 
 template <typename T, int RAD>
 __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ein, T *__restrict__ eout,
                                                        const T *__restrict__ g, const double *__restrict__ G,
-                                                       Level L, unsigned long long *__restrict__ pres)
+                                                       Level L, unsigned long long *__restrict__ pres,
+                                                       int tw, int zc, int ntx, int nty)
 {
-    __shared__ T sin_[RING][NI];  // input planes
-    __shared__ T sgs[RING][NS];   // source on the relaxation-1 region
-    __shared__ T s1[RING][NS];    // relaxation-1 planes
+    constexpr int WPC = sizeof(T) / 4;     // 32-bit words per cell
+    constexpr int LPA = 2 * WPC;           // direct loads per wavefront per staged array and plane
+    constexpr int LPP = 2 * LPA;           // ... per plane (values and source)
+    typedef decltype(res_bits(T(0))) RB;
+    __shared__ T ring[NSLOT][2][kSlotCells];  // [slot][values, source][cell]
+    __shared__ T s1[SXM * SY];                // relaxation-1 plane
+
     const int m = L.m;
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;  // TX x TY2 threads
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY2, z0 = blockIdx.z * ZC2;
-    const int z1 = min(m, z0 + ZC2);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int lane = tid & 63;
+    const unsigned ring_lds = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) T *)&ring[0][0][0]);  // LDS byte address
+    // XCD-grouped tile order: blocks b, b + 8, b + 16 ... (one XCD) take
+    // consecutive tiles
+    int t;
+    {
+        const int nb = gridDim.x, b = blockIdx.x;
+        const int per = nb / kXcds, rem = nb % kXcds, xcd = b % kXcds, k = b / kXcds;
+        t = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
+    }
+    const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
+    const int x0 = bx * tw, y0 = by * TY2, z0 = bz * zc;
+    const int z1 = min(m, z0 + zc);
+    const int IX = tw + 4, SX = tw + 2;
+    const int NI = IX * IY, NS = SX * SY;
+    const int tx = tid % TX, ty = tid / TX;
     const int x = x0 + tx, y = y0 + ty;
-    const bool own = x < m && y < m;
-    const size_t plane = (size_t)m * m;
+    const bool own = tx < tw && x < m && y < m;
+    const size_t plane_bytes = (size_t)m * m * sizeof(T);
+    const unsigned own_off = own ? ((unsigned)y * (unsigned)m + (unsigned)x) * (unsigned)sizeof(T) : 0u;
     const unsigned lam = (unsigned)L.lam, Nf = (unsigned)L.N;
 
-    // input cells staged by this thread (tid, tid + kThreads2), image offsets;
-    // the cells an owned node depends on lie within one reflection (x <= m + 1),
-    // those past it (small levels) are clamped into the grid and never used
+    // image of a coordinate; the cells an owned node depends on lie within
+    // one reflection, those past it (small levels, padding) are clamped into
+    // the grid and never used
     auto img = [&](int c) { return min(max(mir(c, m), 0), m - 1); };
-    unsigned qi[2];
-    const bool two_i = tid + kThreads2 < NI;
-    for (int k = 0; k < 2; ++k) {
-        const int idx = k == 0 ? tid : (two_i ? tid + kThreads2 : 0);
-        const int ly = idx / IX, lx = idx - ly * IX;
-        qi[k] = (unsigned)img(y0 - 2 + ly) * (unsigned)m + (unsigned)img(x0 - 2 + lx);
+    // per-lane byte offsets (within a plane) of this thread's direct loads:
+    // load j of the wavefront fills words (wave * LPA + j) * 64 + lane of the array
+    unsigned qe[LPA], qg[LPA];
+#pragma unroll
+    for (int j = 0; j < LPA; ++j) {
+        const int w = (wave * LPA + j) * 64 + lane;
+        const int cell = w / WPC, half = w % WPC;
+        int ly = cell / IX, lx = cell - ly * IX;
+        if (cell >= NI) ly = lx = 2;  // padding: any cell of the grid
+        qe[j] = ((unsigned)img(y0 - 2 + ly) * (unsigned)m + (unsigned)img(x0 - 2 + lx)) * sizeof(T) + 4 * half;
+        ly = cell / SX, lx = cell - ly * SX;
+        if (cell >= NS) ly = lx = 1;
+        qg[j] = ((unsigned)img(y0 - 1 + ly) * (unsigned)m + (unsigned)img(x0 - 1 + lx)) * sizeof(T) + 4 * half;
     }
-    // relaxation-1 cells of this thread: position in the input and stage planes,
-    // image offsets, x/y Dirichlet faces, offset of their Dirichlet value in G
-    const bool two_s = tid + kThreads2 < NS;
+    // stage input plane zz into slot s
+    auto issue = [&](int zz, int s) {
+        const size_t zo = (size_t)mir(zz, m) * plane_bytes;
+        const char *pe = (const char *)ein + zo, *pg = (const char *)g + zo;
+        const unsigned se = ring_lds + (unsigned)(s * 2 * kSlotCells * sizeof(T)) + wave * LPA * 256;
+        const unsigned sg = se + kSlotCells * sizeof(T);
+#pragma unroll
+        for (int j = 0; j < LPA; ++j) lds_load_word_s(pe, qe[j], se + j * 256);
+#pragma unroll
+        for (int j = 0; j < LPA; ++j) lds_load_word_s(pg, qg[j], sg + j * 256);
+    };
+
+    // relaxation-1 cells of this thread (tid, tid + kThreads2): position in
+    // the input and relaxation-1 planes, x/y Dirichlet faces and the offset
+    // of their Dirichlet value in G
+    const bool one_s = tid < NS, two_s = tid + kThreads2 < NS;
     int sidx[2], sin_c[2];
-    unsigned qs[2], gxy[2];
+    unsigned gxy[2];
     bool sdxy[2];
     for (int k = 0; k < 2; ++k) {
-        const int idx = k == 0 ? tid : (two_s ? tid + kThreads2 : 0);
+        const int idx = k == 0 ? min(tid, NS - 1) : (two_s ? tid + kThreads2 : 0);
         const int ly = idx / SX, lx = idx - ly * SX;
         sidx[k] = idx;
         sin_c[k] = (ly + 1) * IX + lx + 1;
         const int xm = img(x0 - 1 + lx), ym = img(y0 - 1 + ly);
-        qs[k] = (unsigned)ym * (unsigned)m + (unsigned)xm;
         gxy[k] = (unsigned)ym * lam * Nf + (unsigned)xm * lam;
         sdxy[k] = is_dir<2>(xm, ym, 0, m, L.dir);
     }
-    const int c2 = (ty + 1) * SX + tx + 1;  // own node in a relaxation-1 plane
+    const int c2 = (ty + 1) * SX + min(tx, SX - 3) + 1;  // own node in a relaxation-1 plane
 
     const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
     const T Wc = RAD ? T(6) + T(0.5) * T(12) + T(1.0 / 3.0) * T(8) : T(6);
     const T tD = theta / (scale * Wc - a);
-    auto relax = [&](const T (&cc)[3], const T (&cx)[3], const T (&ck)[3], T gv, T &r) {
-        const T uc = cc[1];
-        const T faces = cx[1] + (cc[0] + cc[2]);
+    // one relaxation from the class sums of planes below (0), at (1) and above (2)
+    auto relax = [&](T c0, T c1, T c2v, T x0v, T x1, T x2, T k0, T k1, T k2, T gv, T &r) {
+        const T uc = c1;
+        const T faces = x1 + (c0 + c2v);
         T sum = faces;
         if (RAD) {
-            const T edges = ck[1] + (cx[0] + cx[2]);
-            const T corners = ck[0] + ck[2];
+            const T edges = k1 + (x0v + x2);
+            const T corners = k0 + k2;
             sum = faces + T(0.5) * edges + T(1.0 / 3.0) * corners;
         }
         r = scale * (sum - Wc * uc) + a * uc - gv;
@@ -409,86 +512,89 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
         if (RAD) ck = (P[c - pitch - 1] + P[c - pitch + 1]) + (P[c + pitch - 1] + P[c + pitch + 1]);
     };
 
-    // prefetched input plane (e at the staged cells, g at the relaxation-1 cells)
-    T pe[2] = {T(0), T(0)}, pg[2] = {T(0), T(0)};
-    auto fetch = [&](int zz) {
-        const size_t zo = (size_t)mir(zz, m) * plane;
-        pe[0] = ein[zo + qi[0]];
-        if (two_i) pe[1] = ein[zo + qi[1]];
-        pg[0] = g[zo + qs[0]];
-        if (two_s) pg[1] = g[zo + qs[1]];
-    };
-    auto put = [&](int slot) {
-        sin_[slot][tid] = pe[0];
-        if (two_i) sin_[slot][tid + kThreads2] = pe[1];
-        sgs[slot][sidx[0]] = pg[0];
-        if (two_s) sgs[slot][sidx[1]] = pg[1];
-    };
-    T a_cc[2][3] = {}, a_cx[2][3] = {}, a_ck[2][3] = {};  // input planes zs-1, zs, zs+1 at the relaxation-1 cells
-    T b_cc[3] = {}, b_cx[3] = {}, b_ck[3] = {};           // relaxation-1 planes z-1, z, z+1 at the own node
-    unsigned long long rb = 0;
+    // three-plane windows of class sums, indexed by plane mod 3 (relative to
+    // the chunk's first input plane)
+    T a_cc[2][3] = {}, a_cx[2][3] = {}, a_ck[2][3] = {};  // input planes at the relaxation-1 cells
+    T b_cc[3] = {}, b_cx[3] = {}, b_ck[3] = {};           // relaxation-1 planes at the own node
+    T g_next = T(0), g_cur = T(0);                        // source at the own node, planes zs and z
+    RB rb = 0;
 
-    fetch(z0 - 2);
-    for (int zi = z0 - 2; zi <= z1 + 1; ++zi) {
-        const int slot = (zi + 8) & 3;
-        put(slot);
-        if (zi + 1 <= z1 + 1) fetch(zi + 1);
-        __syncthreads();
-        // relaxation 1 on plane zs = zi - 1
-        const int zs = zi - 1;
+    const int np = (z1 + 1) - (z0 - 2) + 1;  // input planes of the chunk (>= 5)
+    issue(z0 - 2, 0);
+    issue(z0 - 1, 1);
+    // iteration it: input plane zi = z0 - 2 + it arrives (slot it % 3),
+    // relaxation 1 on plane zi - 1, relaxation 2 on plane zi - 2
+    auto step = [&](int it, auto PC) {
+        constexpr int P = decltype(PC)::value;                        // it % 3
+        constexpr int Pm1 = (P + 2) % 3, Pm2 = (P + 1) % 3;            // (it - 1) % 3, (it - 2) % 3
+        if (it + 1 < np) lds_barrier<LPP>();  // plane it + 1 was issued after plane it
+        else lds_barrier<0>();
+        const int zi = z0 - 2 + it;
+        const T *E = &ring[P][0][0];
+#pragma unroll
         for (int k = 0; k < 2; ++k) {
             if (k == 1 && !two_s) break;
-            a_cc[k][0] = a_cc[k][1], a_cc[k][1] = a_cc[k][2];
-            a_cx[k][0] = a_cx[k][1], a_cx[k][1] = a_cx[k][2];
-            a_ck[k][0] = a_ck[k][1], a_ck[k][1] = a_ck[k][2];
-            sums(sin_[slot], sin_c[k], IX, a_cc[k][2], a_cx[k][2], a_ck[k][2]);
+            sums(E, sin_c[k], IX, a_cc[k][P], a_cx[k][P], a_ck[k][P]);
         }
-        if (zs >= z0 - 1) {
+        const int zs = zi - 1;
+        g_cur = g_next;
+        if (it >= 2) {
             const int zsm = mir(zs, m);
             const bool zd = ((L.dir & 16u) && zsm == 0) || ((L.dir & 32u) && zsm == m - 1);
-            const int ss = (zs + 8) & 3;
+            const T *S = &ring[Pm1][1][0];
+            g_next = S[c2];
+#pragma unroll
             for (int k = 0; k < 2; ++k) {
-                if (k == 1 && !two_s) break;
+                if ((k == 0 && !one_s) || (k == 1 && !two_s)) break;
                 T r, v;
                 if (zd || sdxy[k])
                     v = G ? (T)G[(size_t)zsm * lam * Nf * Nf + gxy[k]] : T(0);
                 else
-                    v = relax(a_cc[k], a_cx[k], a_ck[k], sgs[ss][sidx[k]], r);
-                s1[ss][sidx[k]] = v;
+                    v = relax(a_cc[k][Pm2], a_cc[k][Pm1], a_cc[k][P], a_cx[k][Pm2], a_cx[k][Pm1], a_cx[k][P],
+                              a_ck[k][Pm2], a_ck[k][Pm1], a_ck[k][P], S[sidx[k]], r);
+                s1[sidx[k]] = v;
             }
         }
-        __syncthreads();
-        // relaxation 2 on plane z = zs - 1
-        if (zs >= z0 - 1) {
-            b_cc[0] = b_cc[1], b_cc[1] = b_cc[2];
-            b_cx[0] = b_cx[1], b_cx[1] = b_cx[2];
-            b_ck[0] = b_ck[1], b_ck[1] = b_ck[2];
-            sums(s1[(zs + 8) & 3], c2, SX, b_cc[2], b_cx[2], b_ck[2]);
-        }
+        lds_barrier<63>();
+        // the slot of plane it - 1 is free: stage plane it + 2 there
+        if (it + kAhead < np) issue(zi + kAhead, Pm1);
+        if (it >= 2) sums(s1, c2, SX, b_cc[Pm1], b_cx[Pm1], b_ck[Pm1]);  // relaxation-1 plane zs
         const int z = zs - 1;
-        if (z >= z0 && z < z1 && own) {
-            const size_t c = (size_t)z * plane + (size_t)y * m + x;
+        if (it >= 4 && z < z1 && own) {
+            T *orow = (T *)((char *)eout + (size_t)z * plane_bytes);
+            T v;
             if (is_dir<3>(x, y, z, m, L.dir)) {
-                eout[c] = G ? (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)] : T(0);
+                v = G ? (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)] : T(0);
             } else {
                 T r;
-                eout[c] = relax(b_cc, b_cx, b_ck, sgs[(z + 8) & 3][c2], r);
+                // relaxation-1 planes z - 1, z, z + 1 have indices it - 3, it - 2, it - 1
+                v = relax(b_cc[P], b_cc[Pm2], b_cc[Pm1], b_cx[P], b_cx[Pm2], b_cx[Pm1], b_ck[P], b_ck[Pm2],
+                          b_ck[Pm1], g_cur, r);
                 if (pres) {
-                    const unsigned long long b = dbits((double)r);
+                    const RB b = res_bits(r);
                     rb = b > rb ? b : rb;
                 }
             }
+            *(T *)((char *)orow + own_off) = v;
         }
+    };
+    for (int it = 0; it < np; it += 3) {
+        step(it, std::integral_constant<int, 0>());
+        if (it + 1 >= np) break;
+        step(it + 1, std::integral_constant<int, 1>());
+        if (it + 2 >= np) break;
+        step(it + 2, std::integral_constant<int, 2>());
     }
     if (pres) {
+        unsigned long long rw = res_widen(rb);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long o = __shfl_xor(rb, off, 64);
-            rb = o > rb ? o : rb;
+            const unsigned long long o = __shfl_xor(rw, off, 64);
+            rw = o > rw ? o : rw;
         }
-        if ((threadIdx.x & 63) == 0 && rb) {
-            const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z) + threadIdx.x / 64;
-            atomicMax(pres + (b % kRedSlots) * kRedStride, rb);
+        if ((threadIdx.x & 63) == 0 && rw) {
+            const unsigned b = blockIdx.x + threadIdx.x / 64;
+            atomicMax(pres + (b % kRedSlots) * kRedStride, rw);
         }
     }
 }
@@ -686,11 +792,14 @@ void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, co
                      unsigned long long *pres, hipStream_t st)
 {
     const int m = L.m;
-    const dim3 grid((m + TX - 1) / TX, (m + TY2 - 1) / TY2, (m + ZC2 - 1) / ZC2), block(kThreads2);
+    const int tw = (m + (m + TX - 1) / TX - 1) / ((m + TX - 1) / TX);  // balanced tile width <= 64
+    const int nzc = (m + ZC2 - 1) / ZC2, zc = (m + nzc - 1) / nzc;    // balanced z chunk <= ZC2
+    const int ntx = (m + tw - 1) / tw, nty = (m + TY2 - 1) / TY2, nz = (m + zc - 1) / zc;
+    const dim3 grid(ntx * nty * nz), block(kThreads2);
     if (v.radial)
-        hipLaunchKernelGGL((k_sweep3d2<T, 1>), grid, block, 0, st, ein, eout, g, G, L, pres);
+        hipLaunchKernelGGL((k_sweep3d2<T, 1>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty);
     else
-        hipLaunchKernelGGL((k_sweep3d2<T, 0>), grid, block, 0, st, ein, eout, g, G, L, pres);
+        hipLaunchKernelGGL((k_sweep3d2<T, 0>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty);
 }
 
 template void launch_sweep3d2<double>(const Variant &, const Level &, const double *, double *, const double *,

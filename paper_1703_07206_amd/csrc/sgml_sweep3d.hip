@@ -476,7 +476,7 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
     // the input and relaxation-1 planes, x/y Dirichlet faces and the offset
     // of their Dirichlet value in G
     const bool one_s = tid < NS, two_s = tid + kThreads2 < NS;
-    int sidx[2], sin_c[2];
+    int sidx[2], sin_c[2], swr;  // swr: where the first cell's result goes (an unused cell when tid >= NS)
     unsigned gxy[2];
     bool sdxy[2];
     for (int k = 0; k < 2; ++k) {
@@ -488,6 +488,7 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
         gxy[k] = (unsigned)ym * lam * Nf + (unsigned)xm * lam;
         sdxy[k] = is_dir<2>(xm, ym, 0, m, L.dir);
     }
+    swr = one_s ? sidx[0] : SXM * SY - 1;  // tid >= NS only when NS < kThreads2 <= SXM * SY - 1
     const int c2 = (ty + 1) * SX + min(tx, SX - 3) + 1;  // own node in a relaxation-1 plane
 
     const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
@@ -543,16 +544,21 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
             const bool zd = ((L.dir & 16u) && zsm == 0) || ((L.dir & 32u) && zsm == m - 1);
             const T *S = &ring[Pm1][1][0];
             g_next = S[c2];
+            // Dirichlet cells take their value by selection, so that the
+            // common case (no Dirichlet data: zero) runs without branches
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                if ((k == 0 && !one_s) || (k == 1 && !two_s)) break;
-                T r, v;
-                if (zd || sdxy[k])
-                    v = G ? (T)G[(size_t)zsm * lam * Nf * Nf + gxy[k]] : T(0);
-                else
-                    v = relax(a_cc[k][Pm2], a_cc[k][Pm1], a_cc[k][P], a_cx[k][Pm2], a_cx[k][Pm1], a_cx[k][P],
-                              a_ck[k][Pm2], a_ck[k][Pm1], a_ck[k][P], S[sidx[k]], r);
-                s1[sidx[k]] = v;
+                if (k == 1 && !two_s) break;
+                T r;
+                T v = relax(a_cc[k][Pm2], a_cc[k][Pm1], a_cc[k][P], a_cx[k][Pm2], a_cx[k][Pm1], a_cx[k][P],
+                            a_ck[k][Pm2], a_ck[k][Pm1], a_ck[k][P], S[sidx[k]], r);
+                const bool dir = zd || sdxy[k];
+                if (G) {
+                    if (dir) v = (T)G[(size_t)zsm * lam * Nf * Nf + gxy[k]];
+                } else {
+                    v = dir ? T(0) : v;
+                }
+                s1[k == 0 ? swr : sidx[1]] = v;
             }
         }
         lds_barrier<63>();
@@ -560,22 +566,22 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
         if (it + kAhead < np) issue(zi + kAhead, Pm1);
         if (it >= 2) sums(s1, c2, SX, b_cc[Pm1], b_cx[Pm1], b_ck[Pm1]);  // relaxation-1 plane zs
         const int z = zs - 1;
-        if (it >= 4 && z < z1 && own) {
-            T *orow = (T *)((char *)eout + (size_t)z * plane_bytes);
-            T v;
-            if (is_dir<3>(x, y, z, m, L.dir)) {
-                v = G ? (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)] : T(0);
+        if (it >= 4 && z < z1) {
+            T r;
+            // relaxation-1 planes z - 1, z, z + 1 have indices it - 3, it - 2, it - 1
+            T v = relax(b_cc[P], b_cc[Pm2], b_cc[Pm1], b_cx[P], b_cx[Pm2], b_cx[Pm1], b_ck[P], b_ck[Pm2],
+                        b_ck[Pm1], g_cur, r);
+            const bool dir = is_dir<3>(x, y, z, m, L.dir);
+            if (G) {
+                if (dir && own) v = (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)];
             } else {
-                T r;
-                // relaxation-1 planes z - 1, z, z + 1 have indices it - 3, it - 2, it - 1
-                v = relax(b_cc[P], b_cc[Pm2], b_cc[Pm1], b_cx[P], b_cx[Pm2], b_cx[Pm1], b_ck[P], b_ck[Pm2],
-                          b_ck[Pm1], g_cur, r);
-                if (pres) {
-                    const RB b = res_bits(r);
-                    rb = b > rb ? b : rb;
-                }
+                v = dir ? T(0) : v;
             }
-            *(T *)((char *)orow + own_off) = v;
+            if (pres) {
+                const RB b = res_bits(r);
+                rb = (own && !dir && b > rb) ? b : rb;
+            }
+            if (own) *(T *)((char *)eout + (size_t)z * plane_bytes + own_off) = v;
         }
     };
     for (int it = 0; it < np; it += 3) {
@@ -599,37 +605,127 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
     }
 }
 
+// s_waitcnt for a vector-memory count known only at run time (wave-uniform,
+// 0 .. 15): a branch to the matching constant wait.
+__device__ __forceinline__ void wait_vm(int n)
+{
+    switch (n) {
+    case 0: wait_counts<0, 15>(); break;
+    case 1: wait_counts<1, 15>(); break;
+    case 2: wait_counts<2, 15>(); break;
+    case 3: wait_counts<3, 15>(); break;
+    case 4: wait_counts<4, 15>(); break;
+    case 5: wait_counts<5, 15>(); break;
+    case 6: wait_counts<6, 15>(); break;
+    case 7: wait_counts<7, 15>(); break;
+    case 8: wait_counts<8, 15>(); break;
+    case 9: wait_counts<9, 15>(); break;
+    case 10: wait_counts<10, 15>(); break;
+    case 11: wait_counts<11, 15>(); break;
+    case 12: wait_counts<12, 15>(); break;
+    case 13: wait_counts<13, 15>(); break;
+    case 14: wait_counts<14, 15>(); break;
+    default: wait_counts<15, 15>(); break;
+    }
+}
+
 // Interpolation of the pending variation of level nu+1 into level nu (3D,
 // m >= 33), marching in z.  The pending variation at coarse node X is
 // p(X) = ec(X) - efin(2X) (efin = 0 on the level's first visit of a cycle);
 // every fine node takes efin + the trilinear interpolant of p, which at a
 // coarse node is ec itself.  A block owns 64 x 8 fine columns and 16 fine
-// planes: it stages p of the 33 x 5 coarse columns it needs, one coarse plane
-// at a time in a two-plane LDS ring, and streams efin -> efout.
-template <typename T>
+// planes and marches in steps of one coarse plane (two fine planes), with p
+// of the 33 x 5 coarse columns it needs for two coarse planes in an LDS ring.
+// Every input travels straight into LDS (direct-to-LDS loads, as in
+// k_sweep3d2), two steps before it is needed: the stale values of the fine
+// planes (a wavefront loads the cells of its own threads) and ec, efin(2X)
+// of the coarse cells (wavefronts 0 .. 2, one cell per thread).  A step waits
+// once, for the loads issued two steps back: the loads issued one step back
+// may stay in flight, and their count is known.
+constexpr int kProStages = 4;  // fine planes of stale values in the ring (two steps)
+
+template <typename T, bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec, const T *__restrict__ efin,
-                                                        T *__restrict__ efout, int mc, int first)
+                                                        T *__restrict__ efout, int mc)
 {
     constexpr int CXT = TX / 2 + 1, CYT = TY / 2 + 1;  // coarse columns of the tile
-    __shared__ T sp[2][CYT * CXT];
+    constexpr int NC = CXT * CYT;                      // 165 staged coarse cells
+    constexpr int CW = (NC + 63) / 64;                 // wavefronts that stage them
+    constexpr int WPC = sizeof(T) / 4;                 // 32-bit words per cell
+    constexpr int NPA = FIRST ? 1 : 2;                 // staged coarse arrays: ec (and efin(2X))
+    __shared__ T sp[2][NC];                            // p of two coarse planes
+    __shared__ T sc[2][NPA][CW * 64];                  // staged ec, efin(2X) of two coarse planes
+    __shared__ T sst[FIRST ? 1 : kProStages][kThreads];  // stale values, one fine plane per slot
     const int m = 2 * mc - 1;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;  // even
     const int z1 = min(m, z0 + ZC);
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m, cplane = (size_t)mc * mc;
     const unsigned cxy = (unsigned)(own ? y : 0) * (unsigned)m + (unsigned)(own ? x : 0);
-    // the staged coarse cell of this thread (threads beyond CXT * CYT stage nothing)
-    const bool stager = threadIdx.x < CXT * CYT;
-    const int scy = threadIdx.x / CXT, scx = threadIdx.x - scy * CXT;
-    const int X = min(x0 / 2 + scx, mc - 1), Y = min(y0 / 2 + scy, mc - 1);
-    auto stage = [&](int slot, int Z) {
-        if (!stager) return;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid & 63;
+    const bool cwave = wave < CW;
+
+    // direct loads of the coarse cells: load j of a staging wavefront fills
+    // words (wave * WPC + j) * 64 + lane, i.e. cells of its own threads
+    // (beyond the 165 cells: a clamped cell, never used)
+    unsigned qc[WPC], qf[WPC];
+#pragma unroll
+    for (int j = 0; j < WPC; ++j) {
+        const int w = (wave * WPC + j) * 64 + lane;
+        const int cell = min(w / WPC, NC - 1), half = w % WPC;
+        const int cy = cell / CXT, cx = cell - cy * CXT;
+        const int X = min(x0 / 2 + cx, mc - 1), Y = min(y0 / 2 + cy, mc - 1);
+        qc[j] = ((unsigned)Y * (unsigned)mc + (unsigned)X) * sizeof(T) + 4 * half;
+        qf[j] = ((unsigned)(2 * Y) * (unsigned)m + (unsigned)(2 * X)) * sizeof(T) + 4 * half;
+    }
+    // direct loads of the stale values of this wavefront's cells
+    unsigned qst[WPC];
+#pragma unroll
+    for (int j = 0; j < WPC; ++j) {
+        const int w = (wave * WPC + j) * 64 + lane;
+        const int cell = w / WPC, half = w % WPC;
+        const int cx = x0 + cell % TX, cy = y0 + cell / TX;
+        const unsigned off = (cx < m && cy < m) ? (unsigned)cy * (unsigned)m + (unsigned)cx : 0u;
+        qst[j] = off * sizeof(T) + 4 * half;
+    }
+    const unsigned sc_lds = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) T *)&sc[0][0][0]);
+    const unsigned sst_lds = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) T *)&sst[0][0]);
+    // stage coarse plane Z (clamped into the grid) into staging slot Z & 1;
+    // returns the loads this wavefront issued
+    auto issue_coarse = [&](int Z) {
+        if (!cwave) return 0;
         Z = min(Z, mc - 1);
-        T v = ec[(size_t)Z * cplane + (size_t)Y * mc + X];
-        if (!first) v -= efin[(size_t)(2 * Z) * plane + (size_t)(2 * Y) * m + 2 * X];
-        sp[slot][threadIdx.x] = v;
+        const unsigned lds = sc_lds + (unsigned)((Z & 1) * NPA * CW * 64 * sizeof(T)) + wave * WPC * 256;
+        const char *bc = (const char *)ec + (size_t)Z * cplane * sizeof(T);
+#pragma unroll
+        for (int j = 0; j < WPC; ++j) lds_load_word_s(bc, qc[j], lds + j * 256);
+        if (!FIRST) {
+            const char *bf = (const char *)efin + (size_t)(2 * Z) * plane * sizeof(T);
+#pragma unroll
+            for (int j = 0; j < WPC; ++j) lds_load_word_s(bf, qf[j], lds + CW * 64 * sizeof(T) + j * 256);
+        }
+        return NPA * WPC;
+    };
+    // stage the stale values of fine plane z (if it is in the chunk)
+    auto issue_stale = [&](int z) {
+        if (FIRST || z >= z1) return 0;
+        const char *base = (const char *)efin + (size_t)z * plane * sizeof(T);
+        const unsigned lds = sst_lds + (unsigned)((z - z0) % kProStages * kThreads * sizeof(T)) + wave * WPC * 256;
+#pragma unroll
+        for (int j = 0; j < WPC; ++j) lds_load_word_s(base, qst[j], lds + j * 256);
+        return WPC;
+    };
+    // p of the staged coarse plane Z into ring slot Z & 1 (staging threads)
+    auto build_p = [&](int Z) {
+        if (tid < NC) {
+            const T c = sc[Z & 1][0][tid];
+            sp[Z & 1][tid] = FIRST ? c : c - sc[Z & 1][FIRST ? 0 : 1][tid];
+        }
     };
     const int oi = x & 1, oj = y & 1;
     const int c00 = (ty >> 1) * CXT + (tx >> 1);  // coarse cell (X, Y) of this column in the tile
@@ -643,28 +739,58 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
         if (oi && oj) acc += P[c00 + CXT + 1];
         return acc;
     };
-    int Zs = z0 / 2;  // coarse plane in slot Zs & 1
-    stage(Zs & 1, Zs);
-    stage((Zs + 1) & 1, Zs + 1);
-    __syncthreads();
-    T stale_next = (own && !first) ? efin[(size_t)z0 * plane + cxy] : T(0);
-    for (int z = z0; z < z1; ++z) {
-        const int Z = z >> 1, ok = z & 1;
-        if (Z + 1 > Zs + 1) {  // move the ring on: coarse plane Z + 1 replaces Z - 1
-            __syncthreads();  // every thread is done with the plane being replaced
-            stage((Z + 1) & 1, Z + 1);
-            Zs = Z;
+
+    // prologue: coarse planes Zs, Zs + 1 (built now) and the first two fine
+    // planes; then coarse plane Zs + 2 and fine planes z0 + 2, z0 + 3 (in flight)
+    const int Zs = z0 / 2;
+    issue_coarse(Zs);
+    asm volatile("" ::: "memory");
+    wait_counts<0, 15>();
+    asm volatile("" ::: "memory");
+    build_p(Zs);
+    issue_coarse(Zs + 1);
+    issue_stale(z0);
+    issue_stale(z0 + 1);
+    asm volatile("" ::: "memory");
+    wait_counts<0, 15>();
+    asm volatile("" ::: "memory");
+    build_p(Zs + 1);
+    int inflight = issue_coarse(Zs + 2);  // loads issued one step back
+    inflight += issue_stale(z0 + 2);
+    inflight += issue_stale(z0 + 3);
+    for (int z = z0; z < z1; z += 2) {
+        const int Z = z >> 1;
+        if (z > z0) {
+            // the loads of two steps back (coarse plane Z + 1, fine planes z, z + 1) are complete
+            asm volatile("" ::: "memory");
+            wait_vm(inflight);
+            asm volatile("" ::: "memory");
+            __syncthreads();  // every thread is done with p of coarse plane Z - 1
+            build_p(Z + 1);
             __syncthreads();
+            // loads for two steps on: coarse plane Z + 3 (staging slot of Z + 1,
+            // just read), fine planes z + 4, z + 5 (slots of z, z + 1, read below)
+        } else {
+            lds_barrier<63>();
         }
-        const T stale = stale_next;
-        if (z + 1 < z1 && own && !first) stale_next = efin[(size_t)(z + 1) * plane + cxy];
-        if (own) {
-            T acc = in_plane(Z & 1);
-            if (ok) acc += in_plane((Z + 1) & 1);
-            const T w = ok ? T(0.5) * wxy : wxy;
-            efout[(size_t)z * plane + cxy] = stale + w * acc;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            if (z + d >= z1) break;
+            const T stale = FIRST ? T(0) : sst[(z + d - z0) % kProStages][tid];
+            if (own) {
+                T acc = in_plane(Z & 1);
+                if (d) acc += in_plane((Z + 1) & 1);
+                const T w = d ? T(0.5) * wxy : wxy;
+                efout[(size_t)(z + d) * plane + cxy] = stale + w * acc;
+            }
         }
+        asm volatile("" ::: "memory");
+        wait_counts<63, 0>();  // this thread's stale reads are done before their slots are refilled
+        inflight = z + 4 < z1 ? issue_coarse(Z + 3) : 0;  // needed two steps on, if there is such a step
+        inflight += issue_stale(z + 4);
+        inflight += issue_stale(z + 5);
     }
+    wait_counts<0, 15>();  // no load may still write the workgroup's LDS when it ends
 }
 
 // One restriction step (Algorithm 1, eq. (4)) from a 3D level of mf >= 33
@@ -812,7 +938,10 @@ void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first
 {
     const int m = 2 * mc - 1;
     const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + ZC - 1) / ZC), block(kThreads);
-    hipLaunchKernelGGL((k_prolong3d<T>), grid, block, 0, st, ec, ef_in, ef_out, mc, (int)first);
+    if (first)
+        hipLaunchKernelGGL((k_prolong3d<T, true>), grid, block, 0, st, ec, ef_in, ef_out, mc);
+    else
+        hipLaunchKernelGGL((k_prolong3d<T, false>), grid, block, 0, st, ec, ef_in, ef_out, mc);
 }
 
 template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, hipStream_t);

@@ -59,14 +59,14 @@ template <typename T, int RAD, int SIG>
 __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein, T *__restrict__ eout,
                                                       const T *__restrict__ g, const T *__restrict__ sig,
                                                       const double *__restrict__ G, Level L,
-                                                      unsigned long long *__restrict__ pres)
+                                                      unsigned long long *__restrict__ pres, int zc)
 {
     __shared__ T su[RING][NP];
     __shared__ T ss[SIG ? RING : 1][SIG ? NP : 1];
     const int m = L.m;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
-    const int z1 = min(m, z0 + ZC);
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
+    const int z1 = min(m, z0 + zc);
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m;
@@ -646,7 +646,7 @@ constexpr int kProStages = 4;  // fine planes of stale values in the ring (two s
 
 template <typename T, bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec, const T *__restrict__ efin,
-                                                        T *__restrict__ efout, int mc)
+                                                        T *__restrict__ efout, int mc, int zc)
 {
     constexpr int CXT = TX / 2 + 1, CYT = TY / 2 + 1;  // coarse columns of the tile
     constexpr int NC = CXT * CYT;                      // 165 staged coarse cells
@@ -659,8 +659,8 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
     const int m = 2 * mc - 1;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;  // even
-    const int z1 = min(m, z0 + ZC);
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;  // zc even: z0 even
+    const int z1 = min(m, z0 + zc);
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m, cplane = (size_t)mc * mc;
@@ -805,13 +805,14 @@ constexpr int RFX = 2 * RCX + 1, RFY = 2 * RCY + 1, RNP = RFX * RFY;  // staged 
 constexpr int RLI = (RNP + kThreads - 1) / kThreads;               // staged cells per thread
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_restrict3d(const T *__restrict__ fine, T *__restrict__ coarse, int mc)
+__global__ __launch_bounds__(kThreads) void k_restrict3d(const T *__restrict__ fine, T *__restrict__ coarse, int mc,
+                                                         int zc)
 {
     __shared__ T sf[2][RNP];
     const int mf = 2 * mc - 1;
     const int tx = threadIdx.x % RCX, ty = threadIdx.x / RCX;
-    const int X0 = blockIdx.x * RCX, Y0 = blockIdx.y * RCY, Z0 = blockIdx.z * ZC;
-    const int Z1 = min(mc, Z0 + ZC);
+    const int X0 = blockIdx.x * RCX, Y0 = blockIdx.y * RCY, Z0 = blockIdx.z * zc;
+    const int Z1 = min(mc, Z0 + zc);
     const int X = X0 + tx, Y = Y0 + ty;
     const bool own = X < mc && Y < mc;
     const size_t fplane = (size_t)mf * mf;
@@ -879,6 +880,18 @@ __global__ __launch_bounds__(kThreads) void k_restrict3d(const T *__restrict__ f
 
 bool sweep3d_supported(int m) { return m >= 33; }
 
+// z chunk of a z-marching launch: at most zmax planes, fewer on small levels
+// so that the grid still has about kMinBlocks workgroups.  A chunk costs a
+// few halo planes, which a small level can afford; a long chain of dependent
+// plane steps on a handful of workgroups it cannot.  Rounded up to `multiple`.
+static int z_chunk(int m, int blocks_xy, int zmax, int multiple)
+{
+    constexpr long long kMinBlocks = 1024;
+    int zc = (int)((long long)m * blocks_xy / kMinBlocks);
+    zc = zc < 1 ? 1 : (zc > zmax ? zmax : zc);
+    return (zc + multiple - 1) / multiple * multiple;
+}
+
 template <typename T>
 void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
 {
@@ -902,15 +915,16 @@ void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, con
                     const double *G, unsigned long long *pres, hipStream_t st)
 {
     const int m = L.m;
-    const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + ZC - 1) / ZC), block(kThreads);
+    const int bx = (m + TX - 1) / TX, by = (m + TY - 1) / TY, zc = z_chunk(m, bx * by, ZC, 1);
+    const dim3 grid(bx, by, (m + zc - 1) / zc), block(kThreads);
     if (v.radial && v.sigma)
-        hipLaunchKernelGGL((k_sweep3d<T, 1, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres);
+        hipLaunchKernelGGL((k_sweep3d<T, 1, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
     else if (v.radial)
-        hipLaunchKernelGGL((k_sweep3d<T, 1, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres);
+        hipLaunchKernelGGL((k_sweep3d<T, 1, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
     else if (v.sigma)
-        hipLaunchKernelGGL((k_sweep3d<T, 0, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres);
+        hipLaunchKernelGGL((k_sweep3d<T, 0, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
     else
-        hipLaunchKernelGGL((k_sweep3d<T, 0, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres);
+        hipLaunchKernelGGL((k_sweep3d<T, 0, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
 }
 
 template <typename T>
@@ -919,8 +933,10 @@ void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, co
 {
     const int m = L.m;
     const int tw = (m + (m + TX - 1) / TX - 1) / ((m + TX - 1) / TX);  // balanced tile width <= 64
-    const int nzc = (m + ZC2 - 1) / ZC2, zc = (m + nzc - 1) / nzc;    // balanced z chunk <= ZC2
-    const int ntx = (m + tw - 1) / tw, nty = (m + TY2 - 1) / TY2, nz = (m + zc - 1) / zc;
+    const int ntx = (m + tw - 1) / tw, nty = (m + TY2 - 1) / TY2;
+    const int zt = z_chunk(m, ntx * nty, ZC2, 1);                      // target z chunk
+    const int nzc = (m + zt - 1) / zt, zc = (m + nzc - 1) / nzc;       // balanced
+    const int nz = (m + zc - 1) / zc;
     const dim3 grid(ntx * nty * nz), block(kThreads2);
     if (v.radial)
         hipLaunchKernelGGL((k_sweep3d2<T, 1>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty);
@@ -937,11 +953,12 @@ template <typename T>
 void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)
 {
     const int m = 2 * mc - 1;
-    const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + ZC - 1) / ZC), block(kThreads);
+    const int bx = (m + TX - 1) / TX, by = (m + TY - 1) / TY, zc = z_chunk(m, bx * by, ZC, 2);
+    const dim3 grid(bx, by, (m + zc - 1) / zc), block(kThreads);
     if (first)
-        hipLaunchKernelGGL((k_prolong3d<T, true>), grid, block, 0, st, ec, ef_in, ef_out, mc);
+        hipLaunchKernelGGL((k_prolong3d<T, true>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc);
     else
-        hipLaunchKernelGGL((k_prolong3d<T, false>), grid, block, 0, st, ec, ef_in, ef_out, mc);
+        hipLaunchKernelGGL((k_prolong3d<T, false>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc);
 }
 
 template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, hipStream_t);
@@ -950,8 +967,9 @@ template void launch_prolong3d<float>(int, const float *, const float *, float *
 template <typename T>
 void launch_restrict3d(int mc, const T *fine, T *coarse, hipStream_t st)
 {
-    const dim3 grid((mc + RCX - 1) / RCX, (mc + RCY - 1) / RCY, (mc + ZC - 1) / ZC), block(kThreads);
-    hipLaunchKernelGGL((k_restrict3d<T>), grid, block, 0, st, fine, coarse, mc);
+    const int bx = (mc + RCX - 1) / RCX, by = (mc + RCY - 1) / RCY, zc = z_chunk(mc, bx * by, ZC, 1);
+    const dim3 grid(bx, by, (mc + zc - 1) / zc), block(kThreads);
+    hipLaunchKernelGGL((k_restrict3d<T>), grid, block, 0, st, fine, coarse, mc, zc);
 }
 
 template void launch_restrict3d<double>(int, const double *, double *, hipStream_t);

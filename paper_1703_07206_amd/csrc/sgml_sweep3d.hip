@@ -55,24 +55,49 @@ __device__ __forceinline__ StageCells stage_cells(int x0, int y0, int m)
 // registers before plane z is computed and stored to LDS after, so their
 // latency overlaps the computation, and one barrier per plane suffices (the
 // plane being written is never one being read).
-template <typename T, int RAD, int SIG>
-__global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein, T *__restrict__ eout,
-                                                      const T *__restrict__ g, const T *__restrict__ sig,
-                                                      const double *__restrict__ G, Level L,
-                                                      unsigned long long *__restrict__ pres, int zc)
+// Tile shapes of the single relaxation: 64 x 8 columns, and 4 x 128 for the
+// last column of a level whose other columns fill whole 64-wide tiles
+// (m = 64 k + 1, every level from 65 on): that column then costs 1/16 of a
+// tile column of wavefronts instead of a whole one.
+constexpr int kColW = 4, kColRows = kThreads / kColW;
+constexpr int NPMAX = (kColW + 2) * (kColRows + 2);  // staged cells of the larger shape (780)
+static_assert(NP <= NPMAX && NPMAX <= 2 * kThreads, "two staged cells per thread");
+
+// StageCells for a tile TW columns wide (kThreads / TW rows); cells past one
+// reflection (small levels) are clamped into the grid and never used.
+template <int TW>
+__device__ __forceinline__ StageCells stage_cells_t(int x0, int y0, int m)
 {
-    __shared__ T su[RING][NP];
-    __shared__ T ss[SIG ? RING : 1][SIG ? NP : 1];
+    constexpr int PXT = TW + 2, NPT = PXT * (kThreads / TW + 2);
+    auto img = [&](int c) { return min(max(mir(c, m), 0), m - 1); };
+    StageCells c;
+    for (int k = 0; k < 2; ++k) {
+        const int idx = (int)threadIdx.x + k * kThreads;
+        const int i = idx < NPT ? idx : 0;
+        c.ly[k] = i / PXT;
+        c.lx[k] = i - c.ly[k] * PXT;
+        c.q[k] = (unsigned)img(y0 - 1 + c.ly[k]) * (unsigned)m + (unsigned)img(x0 - 1 + c.lx[k]);
+    }
+    c.two = (int)threadIdx.x + kThreads < NPT;
+    return c;
+}
+
+template <typename T, int RAD, int SIG, int TW>
+__device__ __forceinline__ void sweep3d_tile(T (*su)[NPMAX], T (*ss)[NPMAX], const T *__restrict__ ein,
+                                             T *__restrict__ eout, const T *__restrict__ g,
+                                             const T *__restrict__ sig, const double *__restrict__ G,
+                                             const Level &L, unsigned long long *__restrict__ pres, int x0,
+                                             int y0, int z0, int z1)
+{
+    constexpr int PXT = TW + 2;  // pitch of a staged plane
     const int m = L.m;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
-    const int z1 = min(m, z0 + zc);
+    const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m;
     const unsigned cxy = (unsigned)(own ? y : 0) * (unsigned)m + (unsigned)(own ? x : 0);
-    const StageCells cells = stage_cells(x0, y0, m);
-    const int ctr = (ty + 1) * PX + tx + 1;  // this thread's node in a staged plane
+    const StageCells cells = stage_cells_t<TW>(x0, y0, m);
+    const int ctr = (ty + 1) * PXT + tx + 1;  // this thread's node in a staged plane
 
     T pe[2] = {T(0), T(0)}, ps[2] = {T(1), T(1)};
     auto fetch = [&](int zz) {
@@ -105,8 +130,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
     auto plane_sums = [&](int slot, int at) {
         const T *P = su[slot];
         cc[at] = P[ctr];
-        cx[at] = (P[ctr - 1] + P[ctr + 1]) + (P[ctr - PX] + P[ctr + PX]);
-        if (RAD) ck[at] = (P[ctr - PX - 1] + P[ctr - PX + 1]) + (P[ctr + PX - 1] + P[ctr + PX + 1]);
+        cx[at] = (P[ctr - 1] + P[ctr + 1]) + (P[ctr - PXT] + P[ctr + PXT]);
+        if (RAD) ck[at] = (P[ctr - PXT - 1] + P[ctr - PXT + 1]) + (P[ctr + PXT - 1] + P[ctr + PXT + 1]);
     };
     fetch(z0 - 1);
     put(0);
@@ -168,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
                         for (int dx = -1; dx <= 1; ++dx) {
                             const int cls = (dx != 0) + (dy != 0) + (dz != 0);
                             if (cls == 0 || (!RAD && cls != 1)) continue;
-                            const int o = ctr + dy * PX + dx;
+                            const int o = ctr + dy * PXT + dx;
                             const T du = Pu[dz + 1][o] - uc;
                             const T t = Ps[dz + 1][o] + sgc;
                             acc[cls - 1] += t * du;
@@ -200,6 +225,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein,
             atomicMax(pres + (b % kRedSlots) * kRedStride, rb);
         }
     }
+}
+
+template <typename T, int RAD, int SIG>
+__global__ __launch_bounds__(kThreads) void k_sweep3d(const T *__restrict__ ein, T *__restrict__ eout,
+                                                      const T *__restrict__ g, const T *__restrict__ sig,
+                                                      const double *__restrict__ G, Level L,
+                                                      unsigned long long *__restrict__ pres, int zc, int ntx,
+                                                      int nty, int ncy)
+{
+    __shared__ T su[RING][NPMAX];
+    __shared__ T ss[SIG ? RING : 1][NPMAX];
+    // per z chunk: ntx x nty tiles of 64 x 8, then ncy column tiles of 4 x 128
+    const int per = ntx * nty + ncy;
+    const int bz = blockIdx.x / per, r = blockIdx.x - bz * per;
+    const int z0 = bz * zc, z1 = min(L.m, z0 + zc);
+    if (r < ntx * nty)
+        sweep3d_tile<T, RAD, SIG, TX>(su, ss, ein, eout, g, sig, G, L, pres, (r % ntx) * TX, (r / ntx) * TY, z0, z1);
+    else
+        sweep3d_tile<T, RAD, SIG, kColW>(su, ss, ein, eout, g, sig, G, L, pres, ntx * TX, (r - ntx * nty) * kColRows,
+                                         z0, z1);
 }
 
 // End of a cycle on a 3D level 0 (recurrence of Sec. 2, FP64), marching in
@@ -915,16 +960,20 @@ void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, con
                     const double *G, unsigned long long *pres, hipStream_t st)
 {
     const int m = L.m;
-    const int bx = (m + TX - 1) / TX, by = (m + TY - 1) / TY, zc = z_chunk(m, bx * by, ZC, 1);
-    const dim3 grid(bx, by, (m + zc - 1) / zc), block(kThreads);
+    // m = 64 k + 1: k tiles of 64 columns and the last column in 4 x 128 tiles
+    const bool split = m >= 65 && (m - 1) % TX == 0;
+    const int ntx = split ? (m - 1) / TX : (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
+    const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
+    const int zc = z_chunk(m, ntx * nty + ncy, ZC, 1);
+    const dim3 grid((ntx * nty + ncy) * ((m + zc - 1) / zc)), block(kThreads);
     if (v.radial && v.sigma)
-        hipLaunchKernelGGL((k_sweep3d<T, 1, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
+        hipLaunchKernelGGL((k_sweep3d<T, 1, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc, ntx, nty, ncy);
     else if (v.radial)
-        hipLaunchKernelGGL((k_sweep3d<T, 1, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
+        hipLaunchKernelGGL((k_sweep3d<T, 1, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc, ntx, nty, ncy);
     else if (v.sigma)
-        hipLaunchKernelGGL((k_sweep3d<T, 0, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
+        hipLaunchKernelGGL((k_sweep3d<T, 0, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc, ntx, nty, ncy);
     else
-        hipLaunchKernelGGL((k_sweep3d<T, 0, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc);
+        hipLaunchKernelGGL((k_sweep3d<T, 0, 0>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc, ntx, nty, ncy);
 }
 
 template <typename T>

@@ -448,18 +448,22 @@ __device__ __forceinline__ unsigned long long res_widen(unsigned long long b) { 
 // the march is unrolled by three so that slots and windows are fixed per copy.
 constexpr int NSLOT = 3, kAhead = NSLOT - 1;
 
-template <typename T, int RAD>
-__global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ein, T *__restrict__ eout,
-                                                       const T *__restrict__ g, const double *__restrict__ G,
-                                                       Level L, unsigned long long *__restrict__ pres,
-                                                       int tw, int zc, int ntx, int nty)
+// One tile of the paired relaxation: TWL lanes across (tw <= TWL of them own
+// columns x0 .. x0 + tw - 1), kThreads2 / TWL rows from y0, planes z0 .. z1 - 1.
+template <typename T, int RAD, int TWL>
+__device__ __forceinline__ void pair3d_tile(T (*ring)[2][kSlotCells], T *s1, const T *__restrict__ ein,
+                                            T *__restrict__ eout, const T *__restrict__ g,
+                                            const double *__restrict__ G, const Level &L,
+                                            unsigned long long *__restrict__ pres, int x0, int y0, int z0, int z1,
+                                            int tw)
 {
     constexpr int WPC = sizeof(T) / 4;     // 32-bit words per cell
     constexpr int LPA = 2 * WPC;           // direct loads per wavefront per staged array and plane
     constexpr int LPP = 2 * LPA;           // ... per plane (values and source)
+    constexpr int THL = kThreads2 / TWL;   // rows of the tile
+    constexpr int TWMAX = TWL == TX ? TX : 1;  // widest tw of the shape (the column tiles own one column)
+    static_assert((TWMAX + 4) * (THL + 4) <= kSlotCells && (TWMAX + 2) * (THL + 2) <= SXM * SY, "tile fits the LDS");
     typedef decltype(res_bits(T(0))) RB;
-    __shared__ T ring[NSLOT][2][kSlotCells];  // [slot][values, source][cell]
-    __shared__ T s1[SXM * SY];                // relaxation-1 plane
 
     const int m = L.m;
     const int tid = threadIdx.x;
@@ -467,20 +471,9 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
     const int lane = tid & 63;
     const unsigned ring_lds = __builtin_amdgcn_readfirstlane(
         (unsigned)(size_t)(__attribute__((address_space(3))) T *)&ring[0][0][0]);  // LDS byte address
-    // XCD-grouped tile order: blocks b, b + 8, b + 16 ... (one XCD) take
-    // consecutive tiles
-    int t;
-    {
-        const int nb = gridDim.x, b = blockIdx.x;
-        const int per = nb / kXcds, rem = nb % kXcds, xcd = b % kXcds, k = b / kXcds;
-        t = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
-    }
-    const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
-    const int x0 = bx * tw, y0 = by * TY2, z0 = bz * zc;
-    const int z1 = min(m, z0 + zc);
     const int IX = tw + 4, SX = tw + 2;
-    const int NI = IX * IY, NS = SX * SY;
-    const int tx = tid % TX, ty = tid / TX;
+    const int NI = IX * (THL + 4), NS = SX * (THL + 2);
+    const int tx = tid % TWL, ty = tid / TWL;
     const int x = x0 + tx, y = y0 + ty;
     const bool own = tx < tw && x < m && y < m;
     const size_t plane_bytes = (size_t)m * m * sizeof(T);
@@ -648,6 +641,35 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
             atomicMax(pres + (b % kRedSlots) * kRedStride, rw);
         }
     }
+}
+
+// The paired relaxation's launch: per z chunk, ntx x nty tiles of tw x 8
+// columns, then ncy tiles of 4 x 128 for the last column of a 64k + 1 level
+// (as in k_sweep3d).  Consecutive tiles go to one XCD (dispatch deals blocks
+// to the XCDs in turn), so that the halo rows two neighbouring tiles share are
+// read through the same L2.
+template <typename T, int RAD>
+__global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ein, T *__restrict__ eout,
+                                                       const T *__restrict__ g, const double *__restrict__ G,
+                                                       Level L, unsigned long long *__restrict__ pres,
+                                                       int tw, int zc, int ntx, int nty, int ncy)
+{
+    __shared__ T ring[NSLOT][2][kSlotCells];  // [slot][values, source][cell]
+    __shared__ T s1[SXM * SY];                // relaxation-1 plane
+    int t;
+    {
+        const int nb = gridDim.x, b = blockIdx.x;
+        const int per = nb / kXcds, rem = nb % kXcds, xcd = b % kXcds, k = b / kXcds;
+        t = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
+    }
+    const int per = ntx * nty + ncy;
+    const int bz = t / per, r = t - bz * per;
+    const int z0 = bz * zc, z1 = min(L.m, z0 + zc);
+    if (r < ntx * nty)
+        pair3d_tile<T, RAD, TX>(ring, s1, ein, eout, g, G, L, pres, (r % ntx) * tw, (r / ntx) * TY2, z0, z1, tw);
+    else
+        pair3d_tile<T, RAD, kColW>(ring, s1, ein, eout, g, G, L, pres, ntx * tw, (r - ntx * nty) * kColRows, z0,
+                                   z1, 1);
 }
 
 // s_waitcnt for a vector-memory count known only at run time (wave-uniform,
@@ -981,16 +1003,20 @@ void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, co
                      unsigned long long *pres, hipStream_t st)
 {
     const int m = L.m;
-    const int tw = (m + (m + TX - 1) / TX - 1) / ((m + TX - 1) / TX);  // balanced tile width <= 64
-    const int ntx = (m + tw - 1) / tw, nty = (m + TY2 - 1) / TY2;
-    const int zt = z_chunk(m, ntx * nty, ZC2, 1);                      // target z chunk
+    // m = 64 k + 1: k tiles of 64 columns and the last column in 4 x 128
+    // tiles; otherwise balanced tile widths (at most 64)
+    const bool split = m >= 65 && (m - 1) % TX == 0;
+    const int tw = split ? TX : (m + (m + TX - 1) / TX - 1) / ((m + TX - 1) / TX);
+    const int ntx = split ? (m - 1) / TX : (m + tw - 1) / tw, nty = (m + TY2 - 1) / TY2;
+    const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
+    const int zt = z_chunk(m, ntx * nty + ncy, ZC2, 1);                // target z chunk
     const int nzc = (m + zt - 1) / zt, zc = (m + nzc - 1) / nzc;       // balanced
     const int nz = (m + zc - 1) / zc;
-    const dim3 grid(ntx * nty * nz), block(kThreads2);
+    const dim3 grid((ntx * nty + ncy) * nz), block(kThreads2);
     if (v.radial)
-        hipLaunchKernelGGL((k_sweep3d2<T, 1>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty);
+        hipLaunchKernelGGL((k_sweep3d2<T, 1>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty, ncy);
     else
-        hipLaunchKernelGGL((k_sweep3d2<T, 0>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty);
+        hipLaunchKernelGGL((k_sweep3d2<T, 0>), grid, block, 0, st, ein, eout, g, G, L, pres, tw, zc, ntx, nty, ncy);
 }
 
 template void launch_sweep3d2<double>(const Variant &, const Level &, const double *, double *, const double *,

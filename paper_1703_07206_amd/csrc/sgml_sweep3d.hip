@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
 //
 // The input planes (values on the tile plus a two-node halo, source on the
 // relaxation-1 region) travel from global memory straight into a ring of
-// LDS slots (direct-to-LDS loads, no registers), kDepth planes ahead of the
+// LDS slots (direct-to-LDS loads, no registers), two planes ahead of the
 // plane being relaxed, so that a block keeps several planes of loads in
 // flight.  Every wavefront issues the same number of those loads per plane
 // (the slots are padded to two loads per thread), which makes the number of

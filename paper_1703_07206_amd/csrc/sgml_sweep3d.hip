@@ -55,6 +55,17 @@ __device__ __forceinline__ StageCells stage_cells(int x0, int y0, int m)
 // registers before plane z is computed and stored to LDS after, so their
 // latency overlaps the computation, and one barrier per plane suffices (the
 // plane being written is never one being read).
+// Tile index of a block in XCD-grouped order: dispatch deals blocks to the 8
+// XCDs in turn, so blocks b, b + 8, b + 16 ... share an XCD and its L2; they
+// take consecutive tiles, whose shared halo rows then meet in one L2 (used by
+// the paired relaxation).  A bijection of 0 .. nb - 1.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    constexpr int kX = 8;
+    const int per = nb / kX, rem = nb % kX, xcd = b % kX, k = b / kX;
+    return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
+}
+
 // Tile shapes of the single relaxation: 64 x 8 columns, and 4 x 128 for the
 // last column of a level whose other columns fill whole 64-wide tiles
 // (m = 64 k + 1, every level from 65 on): that column then costs 1/16 of a
@@ -403,7 +414,6 @@ constexpr int IXM = TX + 4, IY = TY2 + 4;               // input plane, halo 2 (
 constexpr int SXM = TX + 2, SY = TY2 + 2;               // relaxation-1 plane, halo 1 (at most 66 x 10)
 constexpr int kSlotCells = 2 * kThreads2;               // 1024 cells per staged array of a slot
 static_assert(IXM * IY <= kSlotCells && SXM * SY <= kSlotCells, "two staged cells per thread");
-constexpr int kXcds = 8;
 
 // s_waitcnt: at most VM vector-memory and LGKM LDS operations of this
 // wavefront still outstanding (expcnt not waited for).
@@ -656,12 +666,7 @@ __global__ __launch_bounds__(kThreads2) void k_sweep3d2(const T *__restrict__ ei
 {
     __shared__ T ring[NSLOT][2][kSlotCells];  // [slot][values, source][cell]
     __shared__ T s1[SXM * SY];                // relaxation-1 plane
-    int t;
-    {
-        const int nb = gridDim.x, b = blockIdx.x;
-        const int per = nb / kXcds, rem = nb % kXcds, xcd = b % kXcds, k = b / kXcds;
-        t = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
-    }
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int per = ntx * nty + ncy;
     const int bz = t / per, r = t - bz * per;
     const int z0 = bz * zc, z1 = min(L.m, z0 + zc);
@@ -860,6 +865,197 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
     wait_counts<0, 15>();  // no load may still write the workgroup's LDS when it ends
 }
 
+// The cycle-end pass with a constant coefficient, its inputs loaded straight
+// into LDS two planes ahead (direct-to-LDS loads, as in k_sweep3d2): the
+// values of the cycle (precision T) on the tile plus a one-node halo, and u,
+// s at the tile's nodes.  Each thread converts its two staged cells to FP64
+// (escale, Dirichlet values) into the ring of FP64 planes the stencil reads.
+// A wavefront loads exactly the cells its own threads convert or own, so its
+// own wait suffices before it reads them, and one barrier per plane
+// publishes the converted plane.  Per plane and wavefront: 2 WPC loads of
+// values, 2 of u and 2 of s, whatever the tile.
+template <typename T, int RAD, int TW, bool HASG>
+__device__ __forceinline__ void cycle_end3d_tile(double (*se)[NPMAX], T (*sraw)[kSlotCells],
+                                                 double (*sus)[2][kThreads], const CycleEndArgs &A, int x0,
+                                                 int y0, int z0, int z1, unsigned long long &nb)
+{
+    constexpr int WPC = sizeof(T) / 4;             // 32-bit words per value
+    constexpr int GS = 2 * WPC + 4;                // loads per wavefront and plane
+    constexpr int PXT = TW + 2, NPT = PXT * (kThreads / TW + 2);
+    const Level &L = A.L;
+    const int m = L.m;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int tx = tid % TW, ty = tid / TW;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < m && y < m;
+    const size_t plane = (size_t)m * m;
+    const unsigned cxy = (unsigned)(own ? y : 0) * (unsigned)m + (unsigned)(own ? x : 0);
+    const int ctr = (ty + 1) * PXT + tx + 1;
+    auto img = [&](int c) { return min(max(mir(c, m), 0), m - 1); };
+    const T *__restrict__ E = (const T *)A.e;
+    const double *__restrict__ G = A.G;  // used only when HASG (the first cycle)
+    T *__restrict__ shat = (T *)A.shat;
+
+    // this thread's staged cells (tid, tid + kThreads): offsets and x/y Dirichlet faces
+    unsigned qc[2];
+    bool dxy[2], has[2];
+    for (int k = 0; k < 2; ++k) {
+        const int c = tid + k * kThreads;
+        has[k] = c < NPT;
+        const int ly = (has[k] ? c : 0) / PXT, lx = (has[k] ? c : 0) % PXT;
+        const int xm = img(x0 - 1 + lx), ym = img(y0 - 1 + ly);
+        qc[k] = (unsigned)ym * (unsigned)m + (unsigned)xm;
+        dxy[k] = is_dir<2>(xm, ym, 0, m, L.dir);
+    }
+    // direct loads: values, load j = kk * WPC + jj fills words jj * 64 + lane of
+    // cells kk * kThreads + wave * 64 .. + 63 (this wavefront's threads' cells);
+    // u and s, load j fills words j * 64 + lane of cells wave * 64 .. + 63
+    unsigned qe[2 * WPC], qo[2];
+#pragma unroll
+    for (int j = 0; j < 2 * WPC; ++j) {
+        const int kk = j / WPC, jj = j % WPC;
+        const int w = jj * 64 + lane, c = kk * kThreads + wave * 64 + w / WPC, half = w % WPC;
+        const int cc = c < NPT ? c : 0;
+        const int ly = cc / PXT, lx = cc % PXT;
+        qe[j] = ((unsigned)img(y0 - 1 + ly) * (unsigned)m + (unsigned)img(x0 - 1 + lx)) * sizeof(T) + 4 * half;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int w = j * 64 + lane, c = wave * 64 + w / 2, half = w % 2;
+        const int cx = x0 + c % TW, cy = y0 + c / TW;
+        const unsigned off = (cx < m && cy < m) ? (unsigned)cy * (unsigned)m + (unsigned)cx : 0u;
+        qo[j] = off * 8 + 4 * half;
+    }
+    const unsigned raw_lds = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) T *)&sraw[0][0]);
+    const unsigned us_lds = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) double *)&sus[0][0][0]);
+    // values of plane zz into raw slot (zz - z0) & 1
+    auto issue_e = [&](int zz) {
+        const char *base = (const char *)E + (size_t)mir(zz, m) * plane * sizeof(T);
+        const unsigned lds = raw_lds + (unsigned)(((zz - z0) & 1) * kSlotCells * sizeof(T));
+#pragma unroll
+        for (int j = 0; j < 2 * WPC; ++j) {
+            const int kk = j / WPC, jj = j % WPC;
+            lds_load_word_s(base, qe[j], lds + (unsigned)((kk * kThreads + wave * 64) * sizeof(T)) + jj * 256);
+        }
+    };
+    // u and s of plane zz into slot (zz - z0) & 1
+    auto issue_us = [&](int zz) {
+        const size_t zo = (size_t)zz * plane * sizeof(double);
+        const unsigned lds = us_lds + (unsigned)(((zz - z0) & 1) * 2 * kThreads * sizeof(double)) + wave * 512;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) lds_load_word_s((const char *)A.u + zo, qo[j], lds + j * 256);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            lds_load_word_s((const char *)A.s + zo, qo[j], lds + kThreads * sizeof(double) + j * 256);
+    };
+    // this thread's cells of plane zz, converted into FP64 ring slot (zz - z0 + 1) & 3
+    auto convert = [&](int zz) {
+        const int zm = mir(zz, m);
+        const bool dz = ((L.dir & 16u) && zm == 0) || ((L.dir & 32u) && zm == m - 1);
+        const T *R = sraw[(zz - z0) & 1];
+        double *P = se[(zz - z0 + 1) & 3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!has[k]) continue;
+            double v = A.escale * (double)R[tid + k * kThreads];
+            if (dz || dxy[k]) v = HASG ? G[(size_t)zm * plane + qc[k]] : 0.0;
+            P[tid + k * kThreads] = v;
+        }
+    };
+
+    issue_e(z0 - 1);
+    issue_e(z0);
+    asm volatile("" ::: "memory");
+    wait_counts<0, 15>();
+    asm volatile("" ::: "memory");
+    convert(z0 - 1);
+    convert(z0);
+    asm volatile("" ::: "memory");
+    wait_counts<63, 0>();  // the raw slots are read before they are refilled
+    issue_e(z0 + 1);
+    issue_us(z0);
+    if (z0 + 1 < z1) {
+        issue_e(z0 + 2);
+        issue_us(z0 + 1);
+    }
+    for (int z = z0; z < z1; ++z) {
+        // plane z's group (values of z + 1, u and s of z) is complete; the next one may be in flight
+        asm volatile("" ::: "memory");
+        if (z + 1 < z1) wait_counts<GS, 15>();
+        else wait_counts<0, 15>();
+        asm volatile("" ::: "memory");
+        convert(z + 1);
+        lds_barrier<63>();
+        const double u_c = sus[(z - z0) & 1][0][tid], s_c = sus[(z - z0) & 1][1][tid];
+        if (own) {
+            const size_t c = (size_t)z * plane + cxy;
+            const double *Pe[3] = {se[(z - z0) & 3], se[(z - z0 + 1) & 3], se[(z - z0 + 2) & 3]};
+            const double ec = Pe[1][ctr];
+            A.u[c] = u_c + ec;
+            if (is_dir<3>(x, y, z, m, L.dir)) {
+                A.s[c] = 0.0;
+                if (shat) shat[c] = T(0);
+            } else {
+                double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+                            if (cls == 0 || (!RAD && cls != 1)) continue;
+                            acc[cls - 1] += Pe[dz + 1][ctr + dy * PXT + dx] - ec;
+                        }
+                    }
+                }
+                const double sw = acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2];
+                const double Le = L.scale * sw + L.a * ec;
+                const double sn = s_c - Le;
+                A.s[c] = sn;
+                if (shat) shat[c] = (T)(sn * A.shat_scale);
+                const unsigned long long b = dbits(sn);
+                nb = b > nb ? b : nb;
+            }
+        }
+        asm volatile("" ::: "memory");
+        wait_counts<63, 0>();  // this thread's reads of the slots refilled below are done
+        if (z + 2 < z1) {
+            issue_e(z + 3);
+            issue_us(z + 2);
+        }
+    }
+    wait_counts<0, 15>();  // no load may still write the workgroup's LDS when it ends
+}
+
+template <typename T, int RAD, bool HASG>
+__global__ __launch_bounds__(kThreads) void k_cycle_end3d_lds(CycleEndArgs A, int zc, int ntx, int nty, int ncy)
+{
+    __shared__ double se[4][NPMAX];              // FP64 value planes z - 1, z, z + 1 and the next
+    __shared__ T sraw[2][kSlotCells];            // raw value planes in flight
+    __shared__ double sus[2][2][kThreads];       // u, s of two planes
+    const int per = ntx * nty + ncy;
+    const int bz = blockIdx.x / per, r = blockIdx.x - bz * per;
+    const int z0 = bz * zc, z1 = min(A.L.m, z0 + zc);
+    unsigned long long nb = 0;
+    if (r < ntx * nty)
+        cycle_end3d_tile<T, RAD, TX, HASG>(se, sraw, sus, A, (r % ntx) * TX, (r / ntx) * TY, z0, z1, nb);
+    else
+        cycle_end3d_tile<T, RAD, kColW, HASG>(se, sraw, sus, A, ntx * TX, (r - ntx * nty) * kColRows, z0, z1, nb);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(nb, off, 64);
+        nb = o > nb ? o : nb;
+    }
+    if ((threadIdx.x & 63) == 0 && nb) {
+        const unsigned b = blockIdx.x + threadIdx.x / 64;
+        atomicMax(A.norm + (b % kRedSlots) * kRedStride, nb);
+    }
+}
+
 // One restriction step (Algorithm 1, eq. (4)) from a 3D level of mf >= 33
 // nodes per axis, marching in z.  Coarse node X averages the fine 3^3 block
 // around 2X with weights hat(p/2) per axis over 8; images outside the grid.
@@ -963,15 +1159,30 @@ template <typename T>
 void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
 {
     const int m = a.L.m;
+    if (!v.sigma) {
+        // the constant-coefficient pass with its inputs loaded straight into LDS
+        const bool split = m >= 65 && (m - 1) % TX == 0;
+        const int ntx = split ? (m - 1) / TX : (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
+        const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
+        const int zc = z_chunk(m, ntx * nty + ncy, ZC, 1);
+        const dim3 grid((ntx * nty + ncy) * ((m + zc - 1) / zc)), block(kThreads);
+        // Dirichlet data (the first cycle) in an instantiation of its own, so
+        // that the common one has no load the compiler waits for
+        if (v.radial && a.G)
+            hipLaunchKernelGGL((k_cycle_end3d_lds<T, 1, true>), grid, block, 0, st, a, zc, ntx, nty, ncy);
+        else if (v.radial)
+            hipLaunchKernelGGL((k_cycle_end3d_lds<T, 1, false>), grid, block, 0, st, a, zc, ntx, nty, ncy);
+        else if (a.G)
+            hipLaunchKernelGGL((k_cycle_end3d_lds<T, 0, true>), grid, block, 0, st, a, zc, ntx, nty, ncy);
+        else
+            hipLaunchKernelGGL((k_cycle_end3d_lds<T, 0, false>), grid, block, 0, st, a, zc, ntx, nty, ncy);
+        return;
+    }
     const dim3 grid((m + TX - 1) / TX, (m + TY - 1) / TY, (m + ZC - 1) / ZC), block(kThreads);
-    if (v.radial && v.sigma)
+    if (v.radial)
         hipLaunchKernelGGL((k_cycle_end3d<T, 1, 1>), grid, block, 0, st, a);
-    else if (v.radial)
-        hipLaunchKernelGGL((k_cycle_end3d<T, 1, 0>), grid, block, 0, st, a);
-    else if (v.sigma)
-        hipLaunchKernelGGL((k_cycle_end3d<T, 0, 1>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_cycle_end3d<T, 0, 0>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_cycle_end3d<T, 0, 1>), grid, block, 0, st, a);
 }
 
 template void launch_cycle_end3d<double>(const Variant &, const CycleEndArgs &, hipStream_t);

@@ -1,14 +1,19 @@
-// sgml_sweep3d.hip -- one relaxation of a 3D level, marching in z.
+// sgml_sweep3d.hip -- the 3D level kernels, marching in z: one relaxation,
+// two chained relaxations (sigma = 1), the cycle-end pass, interpolation and
+// restriction.
 //
-// A block owns a 64 x 8 tile of (x, y) columns and a chunk of z planes.
-// Each plane of the level's values (and of the coefficient) is staged once,
-// with a one-node halo, in a ring of LDS planes; a node's 26 (radial)
-// or 6 (axis) neighbours are then read from LDS instead of from L1/L2, and
-// every value crosses the memory hierarchy about once.  Halo cells outside
-// the grid hold the image node, so Neumann faces need no special case.  With
-// a constant coefficient the 26 neighbours are summed by class from per-plane
-// partial sums (face and corner neighbours within a plane), 8 LDS reads per
-// node instead of 26.
+// A block owns a tile of (x, y) columns and a chunk of z planes (sized by the
+// level so that small levels still get many blocks).  Each plane of the
+// level's values (and of the coefficient) is staged once, with its halo, in a
+// ring of LDS planes; a node's 26 (radial) or 6 (axis) neighbours are then
+// read from LDS instead of from L1/L2, and every value crosses the memory
+// hierarchy about once.  Halo cells outside the grid hold the image node, so
+// Neumann faces need no special case.  With a constant coefficient the 26
+// neighbours are summed by class from per-plane partial sums (face and corner
+// neighbours within a plane), 8 LDS reads per node instead of 26.  The paired
+// relaxation, the interpolation and the constant-coefficient cycle end load
+// their planes straight into LDS (global_load_lds_dword) ahead of use.  Every
+// level from 65 on has 64k + 1 columns: the last one runs in 4 x 128 tiles.
 #include "sgml_device.h"
 
 #include <type_traits>

@@ -1064,50 +1064,57 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d_lds(CycleEndArgs A, in
 // One restriction step (Algorithm 1, eq. (4)) from a 3D level of mf >= 33
 // nodes per axis, marching in z.  Coarse node X averages the fine 3^3 block
 // around 2X with weights hat(p/2) per axis over 8; images outside the grid.
-// A block owns 64 x 8 coarse columns; each fine plane is staged once (a
-// 129 x 17 region, two planes in flight, the next one loaded into registers
-// while the current is summed); each thread forms its column's in-plane
-// weighted sum h(zf) and combines h(2Z-1), h(2Z), h(2Z+1) with (1/2, 1, 1/2).
+// A block owns 64 x 8 coarse columns; each fine plane (a 129 x 17 region) is
+// staged once, loaded straight into a three-slot LDS ring two planes ahead of
+// use (direct-to-LDS loads, the same number per wavefront and plane); each
+// thread forms its column's in-plane weighted sum h(zf) and combines
+// h(2Z-1), h(2Z), h(2Z+1) with (1/2, 1, 1/2).
 constexpr int RCX = 64, RCY = 8;                                   // coarse tile
 constexpr int RFX = 2 * RCX + 1, RFY = 2 * RCY + 1, RNP = RFX * RFY;  // staged fine plane
-constexpr int RLI = (RNP + kThreads - 1) / kThreads;               // staged cells per thread
+constexpr int kRSlots = 3;                                         // ring: the plane summed, two in flight
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict3d(const T *__restrict__ fine, T *__restrict__ coarse, int mc,
                                                          int zc)
 {
-    __shared__ T sf[2][RNP];
+    constexpr int WPC = sizeof(T) / 4;                       // 32-bit words per value
+    constexpr int NW = kThreads / 64;                        // wavefronts
+    constexpr int LPW = (RNP * WPC + 64 * NW - 1) / (64 * NW);  // direct loads per wavefront and plane
+    constexpr int SLOT = LPW * NW * 64 / WPC;                // staged cells per slot (padded)
+    __shared__ T sf[kRSlots][SLOT];
     const int mf = 2 * mc - 1;
-    const int tx = threadIdx.x % RCX, ty = threadIdx.x / RCX;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int tx = tid % RCX, ty = tid / RCX;
     const int X0 = blockIdx.x * RCX, Y0 = blockIdx.y * RCY, Z0 = blockIdx.z * zc;
     const int Z1 = min(mc, Z0 + zc);
     const int X = X0 + tx, Y = Y0 + ty;
     const bool own = X < mc && Y < mc;
     const size_t fplane = (size_t)mf * mf;
-    // in-plane image offsets of this thread's staged cells (fine columns
-    // 2 X0 - 1 .. 2 X0 + 2 RCX - 1); the nodes of coarse columns in range need
-    // at most one reflection, the rest (past the grid, for small levels) are
-    // clamped into it and never used
+    // in-plane byte offsets of this wavefront's direct loads: load j fills
+    // words (j * NW + wave) * 64 + lane of a slot (fine columns 2 X0 - 1 ..
+    // 2 X0 + 2 RCX - 1); the nodes of coarse columns in range need at most
+    // one reflection, the rest (past the grid, for small levels, and the
+    // padding) are clamped into it and never used
     auto img = [&](int c) { return min(max(mir(c, mf), 0), mf - 1); };
-    unsigned q[RLI];
+    unsigned q[LPW];
 #pragma unroll
-    for (int k = 0; k < RLI; ++k) {
-        const int idx = (int)threadIdx.x + k * kThreads;
-        const int i = idx < RNP ? idx : 0;
+    for (int j = 0; j < LPW; ++j) {
+        const int w = (j * NW + wave) * 64 + lane;
+        const int cell = w / WPC, half = w % WPC;
+        const int i = cell < RNP ? cell : 0;
         const int ly = i / RFX, lx = i - ly * RFX;
-        q[k] = (unsigned)img(2 * Y0 - 1 + ly) * (unsigned)mf + (unsigned)img(2 * X0 - 1 + lx);
+        q[j] = ((unsigned)img(2 * Y0 - 1 + ly) * (unsigned)mf + (unsigned)img(2 * X0 - 1 + lx)) * sizeof(T) + 4 * half;
     }
-    T pf[RLI];
-    auto fetch = [&](int zf) {
-        const T *__restrict__ pz = fine + (size_t)img(zf) * fplane;
+    const unsigned sf_lds = __builtin_amdgcn_readfirstlane(
+        (unsigned)(size_t)(__attribute__((address_space(3))) T *)&sf[0][0]);
+    // fine planes 2 Z0 - 1 .. 2 Z1 - 1; plane zf goes to slot (zf - zf0) % kRSlots
+    const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
+    auto issue = [&](int zf) {
+        const char *base = (const char *)fine + (size_t)img(zf) * fplane * sizeof(T);
+        const unsigned lds = sf_lds + (unsigned)((zf - zf0) % kRSlots * SLOT * sizeof(T)) + wave * 256;
 #pragma unroll
-        for (int k = 0; k < RLI; ++k)
-            if ((int)threadIdx.x + k * kThreads < RNP) pf[k] = pz[q[k]];
-    };
-    auto put = [&](int slot) {
-#pragma unroll
-        for (int k = 0; k < RLI; ++k)
-            if ((int)threadIdx.x + k * kThreads < RNP) sf[slot][threadIdx.x + k * kThreads] = pf[k];
+        for (int j = 0; j < LPW; ++j) lds_load_word_s(base, q[j], lds + j * NW * 256);
     };
     const int c = (2 * ty + 1) * RFX + 2 * tx + 1;  // fine node 2X, 2Y in the staged plane
     auto hsum = [&](int slot) {
@@ -1117,20 +1124,17 @@ __global__ __launch_bounds__(kThreads) void k_restrict3d(const T *__restrict__ f
         const T r2 = T(0.5) * P[c + RFX - 1] + P[c + RFX] + T(0.5) * P[c + RFX + 1];
         return T(0.5) * r0 + r1 + T(0.5) * r2;
     };
-    // fine planes 2 Z0 - 1 .. 2 Z1 - 1
-    const int zf0 = 2 * Z0 - 1, zf1 = 2 * Z1 - 1;
-    fetch(zf0);
-    put(0);
-    fetch(zf0 + 1);
+    issue(zf0);
+    issue(zf0 + 1);  // zf1 >= zf0 + 2
     T hm = T(0), hc = T(0);  // h(2Z - 1), h(2Z)
     for (int zf = zf0; zf <= zf1; ++zf) {
         const int k = zf - zf0;
-        __syncthreads();  // plane zf is in slot k & 1; the other slot is free
-        if (zf < zf1) {
-            put((k + 1) & 1);  // plane zf + 1 (loaded last iteration)
-            if (zf + 2 <= zf1) fetch(zf + 2);
-        }
-        const T h = hsum(k & 1);
+        // plane zf is complete (plane zf + 1 may be in flight); every thread
+        // is done with the slot of plane zf - 1, refilled below
+        if (zf + 1 <= zf1) lds_barrier<LPW>();
+        else lds_barrier<0>();
+        if (zf + 2 <= zf1) issue(zf + 2);
+        const T h = hsum(k % kRSlots);
         if (k == 0) {
             hm = h;
         } else if (k & 1) {

@@ -63,6 +63,9 @@ CASES = [
     (3, 6, RADIAL, "DDDDDD", True, -0.5, True),
     (3, 6, RADIAL, "DNDDND", False, -0.3, True),
     (3, 6, AXIS, "NDNDDD", False, 0.0, True),
+    # Neumann y+ faces under the last-column (4 x 128) tiles of a 64k + 1 level
+    (3, 6, RADIAL, "NNDNND", True, -0.2, True),
+    (3, 6, AXIS, "DDDNDN", False, -0.1, False),
 ]
 IDS = [f"{d}d-n{n}-{'rad' if s else 'axis'}-{fc}-{'sig' if h else 'one'}" for d, n, s, fc, h, a, g in CASES]
 
@@ -104,8 +107,8 @@ def test_converged_parity_fp64(case):
     assert rel_inf(u_gpu, u_or) < 1e-12
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6], CASES[7], CASES[10], CASES[11]],
-                         ids=[IDS[1], IDS[2], IDS[6], IDS[7], IDS[10], IDS[11]])
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6], CASES[7], CASES[10], CASES[11], CASES[13], CASES[14]],
+                         ids=[IDS[1], IDS[2], IDS[6], IDS[7], IDS[10], IDS[11], IDS[13], IDS[14]])
 def test_mixed_precision(case):
     dim, n, stencil, faces, hetero, a, with_G = case
     wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=400 + n)

@@ -710,9 +710,10 @@ __device__ __forceinline__ void wait_vm(int n)
 // m >= 33), marching in z.  The pending variation at coarse node X is
 // p(X) = ec(X) - efin(2X) (efin = 0 on the level's first visit of a cycle);
 // every fine node takes efin + the trilinear interpolant of p, which at a
-// coarse node is ec itself.  A block owns 64 x 8 fine columns and 16 fine
-// planes and marches in steps of one coarse plane (two fine planes), with p
-// of the 33 x 5 coarse columns it needs for two coarse planes in an LDS ring.
+// coarse node is ec itself.  A block owns 64 x 8 fine columns (4 x 128 for
+// the last column of a 64k + 1 level) and a chunk of fine planes, and marches
+// in steps of one coarse plane (two fine planes), with p of the 33 x 5
+// (3 x 65) coarse columns it needs for two coarse planes in an LDS ring.
 // Every input travels straight into LDS (direct-to-LDS loads, as in
 // k_sweep3d2), two steps before it is needed: the stale values of the fine
 // planes (a wavefront loads the cells of its own threads) and ec, efin(2X)
@@ -721,23 +722,26 @@ __device__ __forceinline__ void wait_vm(int n)
 // may stay in flight, and their count is known.
 constexpr int kProStages = 4;  // fine planes of stale values in the ring (two steps)
 
-template <typename T, bool FIRST>
-__global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec, const T *__restrict__ efin,
-                                                        T *__restrict__ efout, int mc, int zc)
+// largest staged coarse region of the two tile shapes: 3 x 65 (4 x 128 fine
+// columns), against 33 x 5 for 64 x 8
+constexpr int kProNC = 3 * 65, kProCW = (kProNC + 63) / 64;
+
+template <typename T, bool FIRST, int TW>
+__device__ __forceinline__ void prolong3d_tile(T (*sp)[kProNC], T (*sc)[FIRST ? 1 : 2][kProCW * 64],
+                                               T (*sst)[kThreads], const T *__restrict__ ec,
+                                               const T *__restrict__ efin, T *__restrict__ efout, int mc, int x0,
+                                               int y0, int z0, int z1)
 {
-    constexpr int CXT = TX / 2 + 1, CYT = TY / 2 + 1;  // coarse columns of the tile
-    constexpr int NC = CXT * CYT;                      // 165 staged coarse cells
+    constexpr int TH = kThreads / TW;                  // fine rows of the tile
+    constexpr int CXT = TW / 2 + 1, CYT = TH / 2 + 1;  // coarse columns of the tile
+    constexpr int NC = CXT * CYT;                      // staged coarse cells
     constexpr int CW = (NC + 63) / 64;                 // wavefronts that stage them
     constexpr int WPC = sizeof(T) / 4;                 // 32-bit words per cell
     constexpr int NPA = FIRST ? 1 : 2;                 // staged coarse arrays: ec (and efin(2X))
-    __shared__ T sp[2][NC];                            // p of two coarse planes
-    __shared__ T sc[2][NPA][CW * 64];                  // staged ec, efin(2X) of two coarse planes
-    __shared__ T sst[FIRST ? 1 : kProStages][kThreads];  // stale values, one fine plane per slot
+    static_assert(NC <= kProNC && CW <= kProCW, "staging fits");
     const int m = 2 * mc - 1;
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;  // zc even: z0 even
-    const int z1 = min(m, z0 + zc);
+    const int tx = tid % TW, ty = tid / TW;
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < m && y < m;
     const size_t plane = (size_t)m * m, cplane = (size_t)mc * mc;
@@ -747,7 +751,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
 
     // direct loads of the coarse cells: load j of a staging wavefront fills
     // words (wave * WPC + j) * 64 + lane, i.e. cells of its own threads
-    // (beyond the 165 cells: a clamped cell, never used)
+    // (beyond the staged cells: a clamped cell, never used)
     unsigned qc[WPC], qf[WPC];
 #pragma unroll
     for (int j = 0; j < WPC; ++j) {
@@ -764,7 +768,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
     for (int j = 0; j < WPC; ++j) {
         const int w = (wave * WPC + j) * 64 + lane;
         const int cell = w / WPC, half = w % WPC;
-        const int cx = x0 + cell % TX, cy = y0 + cell / TX;
+        const int cx = x0 + cell % TW, cy = y0 + cell / TW;
         const unsigned off = (cx < m && cy < m) ? (unsigned)cy * (unsigned)m + (unsigned)cx : 0u;
         qst[j] = off * sizeof(T) + 4 * half;
     }
@@ -777,14 +781,14 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
     auto issue_coarse = [&](int Z) {
         if (!cwave) return 0;
         Z = min(Z, mc - 1);
-        const unsigned lds = sc_lds + (unsigned)((Z & 1) * NPA * CW * 64 * sizeof(T)) + wave * WPC * 256;
+        const unsigned lds = sc_lds + (unsigned)((Z & 1) * NPA * kProCW * 64 * sizeof(T)) + wave * WPC * 256;
         const char *bc = (const char *)ec + (size_t)Z * cplane * sizeof(T);
 #pragma unroll
         for (int j = 0; j < WPC; ++j) lds_load_word_s(bc, qc[j], lds + j * 256);
         if (!FIRST) {
             const char *bf = (const char *)efin + (size_t)(2 * Z) * plane * sizeof(T);
 #pragma unroll
-            for (int j = 0; j < WPC; ++j) lds_load_word_s(bf, qf[j], lds + CW * 64 * sizeof(T) + j * 256);
+            for (int j = 0; j < WPC; ++j) lds_load_word_s(bf, qf[j], lds + kProCW * 64 * sizeof(T) + j * 256);
         }
         return NPA * WPC;
     };
@@ -868,6 +872,27 @@ __global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec
         inflight += issue_stale(z + 5);
     }
     wait_counts<0, 15>();  // no load may still write the workgroup's LDS when it ends
+}
+
+// The interpolation's launch: per z chunk, ntx x nty tiles of 64 x 8 fine
+// columns, then ncy tiles of 4 x 128 for the last column of a 64k + 1 level.
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_prolong3d(const T *__restrict__ ec, const T *__restrict__ efin,
+                                                        T *__restrict__ efout, int mc, int zc, int ntx, int nty,
+                                                        int ncy)
+{
+    __shared__ T sp[2][kProNC];                            // p of two coarse planes
+    __shared__ T sc[2][FIRST ? 1 : 2][kProCW * 64];        // staged ec, efin(2X) of two coarse planes
+    __shared__ T sst[FIRST ? 1 : kProStages][kThreads];    // stale values, one fine plane per slot
+    const int m = 2 * mc - 1;
+    const int per = ntx * nty + ncy;
+    const int bz = blockIdx.x / per, r = blockIdx.x - bz * per;
+    const int z0 = bz * zc, z1 = min(m, z0 + zc);  // zc even: z0 even
+    if (r < ntx * nty)
+        prolong3d_tile<T, FIRST, TX>(sp, sc, sst, ec, efin, efout, mc, (r % ntx) * TX, (r / ntx) * TY, z0, z1);
+    else
+        prolong3d_tile<T, FIRST, kColW>(sp, sc, sst, ec, efin, efout, mc, ntx * TX, (r - ntx * nty) * kColRows, z0,
+                                        z1);
 }
 
 // The cycle-end pass with a constant coefficient, its inputs loaded straight
@@ -1248,12 +1273,16 @@ template <typename T>
 void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)
 {
     const int m = 2 * mc - 1;
-    const int bx = (m + TX - 1) / TX, by = (m + TY - 1) / TY, zc = z_chunk(m, bx * by, ZC, 2);
-    const dim3 grid(bx, by, (m + zc - 1) / zc), block(kThreads);
+    // m = 64 k + 1: k tiles of 64 columns and the last column in 4 x 128 tiles
+    const bool split = m >= 65 && (m - 1) % TX == 0;
+    const int ntx = split ? (m - 1) / TX : (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
+    const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
+    const int zc = z_chunk(m, ntx * nty + ncy, ZC, 2);
+    const dim3 grid((ntx * nty + ncy) * ((m + zc - 1) / zc)), block(kThreads);
     if (first)
-        hipLaunchKernelGGL((k_prolong3d<T, true>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc);
+        hipLaunchKernelGGL((k_prolong3d<T, true>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc, ntx, nty, ncy);
     else
-        hipLaunchKernelGGL((k_prolong3d<T, false>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc);
+        hipLaunchKernelGGL((k_prolong3d<T, false>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc, ntx, nty, ncy);
 }
 
 template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, hipStream_t);

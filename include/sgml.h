@@ -112,6 +112,13 @@ typedef struct {
                          passes; 0: chosen per launch (8 for short visits, 48 / 96
                          (FP32 / FP64) for long visits of large levels, 96 for the
                          cycle end), values below 8 act as 8 */
+    int z_chunk;      /* planes each workgroup marches through in the 3D z-marching
+                         passes (relaxation, paired relaxation, interpolation,
+                         restriction, constant-coefficient cycle end) on levels of
+                         at least 33 nodes per axis; 0: chosen per level (about
+                         1024 workgroups, at most 16 / 32 planes), otherwise clamped
+                         to the level (the paired relaxation balances its chunks,
+                         the interpolation rounds up to an even count) */
 } sgml_opts;
 
 #define SGML_HIST 512

@@ -9,6 +9,10 @@
 
 namespace sgml {
 
+// Devices a process may drive (per-device state of the library is kept in
+// arrays of this size).
+constexpr int kMaxDevices = 64;
+
 // Geometry and operator constants of one level of the nested grid
 // (Sec. 2: level nu holds the nodes whose indices are multiples of
 // lam = 2^nu; stored compactly as m^d values, m = 2^(n-nu) + 1).
@@ -60,6 +64,10 @@ constexpr int coarse_threads(int dim) { return dim == 3 ? 512 : 1024; }
 // Dirichlet values stay in global memory.  The largest level a run may touch
 // has coarse_lds_nodes() nodes (a fixed number per thread).
 constexpr int coarse_lds_nodes(int dim) { return dim == 3 ? 5120 : 5120; }
+// k_coarse_lds decodes a node index t into (i, j, k) with one float multiply
+// by 1/m, exact while t < 2^13 (t + 1/2 stays 1/(2m) away from a multiple of m)
+static_assert(coarse_lds_nodes(2) < (1 << 13) && coarse_lds_nodes(3) < (1 << 13),
+              "the coarse kernel's float index decode needs levels below 2^13 nodes");
 struct LdsOp {
     int kind;         // kOp*
     int m;            // nodes per axis of the level written
@@ -118,6 +126,7 @@ struct CycleEndArgs {
     void *g1;             // 2D: next cycle's level-1 source (restriction of the new source) or null
     Level L;
     int chunk;            // rows per wavefront (2D)
+    int zchunk;           // planes per workgroup (3D z-marching), 0: chosen per level
 };
 
 // Precision-generic launchers (T = double or float); all enqueue on `st`.
@@ -155,14 +164,15 @@ void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
 bool sweep3d_supported(int m);
 template <typename T>
 void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st);
+// `zreq` (here and below): planes each workgroup marches, 0 = chosen per level.
 template <typename T>
 void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
-                    const double *G, unsigned long long *pres, hipStream_t st);
+                    const double *G, unsigned long long *pres, int zreq, hipStream_t st);
 // Two chained relaxations of a 3D level with sigma = 1 (m >= 33) in one
 // z-marching pass: ein -> (relaxation) -> (relaxation) -> eout.
 template <typename T>
 void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const double *G,
-                     unsigned long long *pres, hipStream_t st);
+                     unsigned long long *pres, int zreq, hipStream_t st);
 
 template <typename T>
 void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, bool first,
@@ -170,7 +180,7 @@ void launch_prolong(int dim, int mc, const T *ec, const T *ef_in, T *ef_out, boo
 // The same interpolation into a 3D level of m = 2 mc - 1 >= 33 nodes per
 // axis, marching in z with the pending variation staged in LDS.
 template <typename T>
-void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st);
+void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, int zreq, hipStream_t st);
 
 template <typename T>
 void launch_inject(int dim, int mc, const T *ef, T *ec, hipStream_t st);
@@ -179,7 +189,7 @@ template <typename Tin, typename Tout>
 void launch_restrict(int dim, int mc, const Tin *fine, Tout *coarse, hipStream_t st);
 // The same step from a 3D level of 2 mc - 1 >= 33 nodes per axis, marching in z.
 template <typename T>
-void launch_restrict3d(int mc, const T *fine, T *coarse, hipStream_t st);
+void launch_restrict3d(int mc, const T *fine, T *coarse, int zreq, hipStream_t st);
 
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, size_t count, hipStream_t st);

@@ -21,6 +21,7 @@
 #include "sgml_device.h"
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -823,14 +824,22 @@ struct CoarseLdsRun {
         static bool run(const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload, int nstore,
                         size_t bytes, const double *G, unsigned long long *targets, hipStream_t st)
         {
-            static size_t granted = 0;  // dynamic LDS this instantiation may use
-            if (bytes > granted) {
-                if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_lds<T, D, R, S>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
-                    (void)hipGetLastError();
-                    return false;
+            // dynamic LDS this instantiation may use, per device; raised under a
+            // lock and never lowered, so a launch never exceeds what is granted
+            static std::mutex lock;
+            static size_t granted[kMaxDevices] = {};
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return false;
+            {
+                std::lock_guard<std::mutex> guard(lock);
+                if (bytes > granted[dev]) {
+                    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_lds<T, D, R, S>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return false;
+                    }
+                    granted[dev] = bytes;
                 }
-                granted = bytes;
             }
             hipLaunchKernelGGL((k_coarse_lds<T, D, R, S>), dim3(1), dim3(coarse_threads(D)), bytes, st, ops,
                                nops, ops_off, xfer, nload, nstore, G, targets);

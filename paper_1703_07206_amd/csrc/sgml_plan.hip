@@ -221,17 +221,20 @@ double host_max(const sgml_plan *P, int t)
 }
 
 // Profiling: a pair of events around a launch; drained once per cycle.
-hipEvent_t *prof_pair(sgml_plan *P)
+// Returns the index of the pair's first event in P->pev (the pool may grow
+// while a cycle is enqueued, so callers keep indices, not pointers), or -1
+// when no event could be created.
+long prof_pair(sgml_plan *P)
 {
     if (P->pev_used + 2 > P->pev.size()) {
         for (int t = 0; t < 64; ++t) {
             hipEvent_t e;
             // timing only: no system-scope fence (no cache writeback) at each record
-            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
             P->pev.push_back(e);
         }
     }
-    hipEvent_t *pr = &P->pev[P->pev_used];
+    const long pr = (long)P->pev_used;
     P->pev_used += 2;
     return pr;
 }
@@ -243,10 +246,10 @@ double as_double(unsigned long long b)
     return d;
 }
 
-// A launch timed with a pair of events (profiling).
+// A launch timed with a pair of events (profiling): P->pev[ev], P->pev[ev + 1].
 struct Timed {
     int cls, sweeps;
-    hipEvent_t *ev;
+    long ev;
 };
 
 // A cycle compiled to a list of operations (the same list every cycle).
@@ -618,7 +621,7 @@ sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, const void *live_
 // the rest as grid launches; level-0 relaxations timed when profiling.
 template <typename T>
 sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *G, bool profile,
-                    bool use_sweep3d, int chunk, std::vector<Timed> &timed, hipStream_t st)
+                    bool use_sweep3d, int chunk, int zreq, std::vector<Timed> &timed, hipStream_t st)
 {
     const CoarseOp *dev_ops = P->at<CoarseOp>(P->lay.ops);
     const Level *dev_levels = P->at<Level>(P->lay.levels);
@@ -646,14 +649,14 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             a.targets = targets;
             a.L = P->level(o.level);
             const int cls = a.inject ? SGML_PROF_VISIT0_INJ : SGML_PROF_VISIT0;
-            hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
-            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            const long ev = (profile && o.level == 0) ? prof_pair(P) : -1;
+            if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
             if (o.level > 0 && tile_visit_supported(o.m))
                 launch_visit_tile<T>(P->var, a, st);
             else
                 launch_visit2d<T>(P->var, a, st);
-            if (ev) {
-                SGML_HIP(hipEventRecord(ev[1], st));
+            if (ev >= 0) {
+                SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
                 timed.push_back({cls, a.sweeps, ev});
             }
             ++i;
@@ -664,26 +667,26 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             launch_fill<T>((T *)o.out, level_nodes(P->dim, P->n, o.level), T(0), st);
             break;
         case kOpSweep2: {
-            hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
-            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            const long ev = (profile && o.level == 0) ? prof_pair(P) : -1;
+            if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
             launch_sweep3d2<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1, G,
-                               o.target >= 0 ? target(P, o.target) : nullptr, st);
-            if (ev) {
-                SGML_HIP(hipEventRecord(ev[1], st));
+                               o.target >= 0 ? target(P, o.target) : nullptr, zreq, st);
+            if (ev >= 0) {
+                SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
                 timed.push_back({SGML_PROF_SWEEP0, 2, ev});
             }
             break;
         }
         case kOpRestrict:
             if (P->dim == 3 && use_sweep3d && sweep3d_supported(2 * o.m - 1))
-                launch_restrict3d<T>(o.m, (const T *)o.in0, (T *)o.out, st);
+                launch_restrict3d<T>(o.m, (const T *)o.in0, (T *)o.out, zreq, st);
             else
                 launch_restrict<T, T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
             break;
         case kOpProlong:
             if (P->dim == 3 && use_sweep3d && sweep3d_supported(o.m))
                 launch_prolong3d<T>((o.m + 1) / 2, (const T *)o.in0, (const T *)o.in1, (T *)o.out, o.first != 0,
-                                    st);
+                                    zreq, st);
             else
                 launch_prolong<T>(P->dim, (o.m + 1) / 2, (const T *)o.in0, (const T *)o.in1, (T *)o.out,
                                   o.first != 0, st);
@@ -692,17 +695,17 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             launch_inject<T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
             break;
         default: {
-            hipEvent_t *ev = (profile && o.level == 0) ? prof_pair(P) : nullptr;
-            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            const long ev = (profile && o.level == 0) ? prof_pair(P) : -1;
+            if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
             unsigned long long *tg = o.target >= 0 ? target(P, o.target) : nullptr;
             if (P->dim == 3 && use_sweep3d && sweep3d_supported(o.m))
                 launch_sweep3d<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1,
-                                  (const T *)o.in2, G, tg, st);
+                                  (const T *)o.in2, G, tg, zreq, st);
             else
                 launch_sweep<T>(P->var, P->level(o.level), (const T *)o.in0, (T *)o.out, (const T *)o.in1,
                                 (const T *)o.in2, G, tg, st);
-            if (ev) {
-                SGML_HIP(hipEventRecord(ev[1], st));
+            if (ev >= 0) {
+                SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
                 timed.push_back({SGML_PROF_SWEEP0, 1, ev});
             }
             break;
@@ -769,6 +772,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
         rc = upload_ops<T>(P, ops, e, st);
         if (rc != SGML_OK) return rc;
         const int chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
+        const int zreq = o->z_chunk > 0 ? o->z_chunk : 0;                     // 0: per level
         int k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
         if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
         if (g1) launch_restrict<T, T>(P->dim, P->m(1), src0, g1, st);  // cycle 0's level-1 source
@@ -779,13 +783,13 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
             std::vector<Timed> timed;
             P->pev_used = 0;
-            rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, timed, st);
+            rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, zreq, timed, st);
             if (rc != SGML_OK) return rc;
             S.node_updates += updates_per_cycle;
             // next cycle's scaling from the last known residual norm (lagged)
             const int k_next = mixed ? std::ilogb(last) : 0;
-            hipEvent_t *ev = o->profile ? prof_pair(P) : nullptr;
-            if (ev) SGML_HIP(hipEventRecord(ev[0], st));
+            const long ev = o->profile ? prof_pair(P) : -1;
+            if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
             if (row_march || z_march) {
                 CycleEndArgs ca;
                 ca.e = e;
@@ -801,6 +805,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                 ca.g1 = g1;
                 ca.L = L0;
                 ca.chunk = chunk;
+                ca.zchunk = zreq;
                 if (z_march)
                     launch_cycle_end3d<T>(P->var, ca, st);
                 else
@@ -809,8 +814,8 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
                 launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
                                    std::ldexp(1.0, -k_next), target(P, 0), st);
             }
-            if (ev) {
-                SGML_HIP(hipEventRecord(ev[1], st));
+            if (ev >= 0) {
+                SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
                 timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
             }
             SGML_HIP(hipGetLastError());
@@ -818,7 +823,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             if (rc != SGML_OK) return rc;
             for (auto &t : timed) {
                 float ms = 0.f;
-                SGML_HIP(hipEventElapsedTime(&ms, t.ev[0], t.ev[1]));
+                SGML_HIP(hipEventElapsedTime(&ms, P->pev[t.ev], P->pev[t.ev + 1]));
                 S.prof_ms[t.cls] += ms;
                 S.prof_launches[t.cls]++;
                 S.prof_sweeps[t.cls] += t.sweeps;

@@ -1181,11 +1181,14 @@ bool sweep3d_supported(int m) { return m >= 33; }
 // so that the grid still has about kMinBlocks workgroups.  A chunk costs a
 // few halo planes, which a small level can afford; a long chain of dependent
 // plane steps on a handful of workgroups it cannot.  Rounded up to `multiple`.
-static int z_chunk(int m, int blocks_xy, int zmax, int multiple)
+// A positive `req` (the caller's choice) replaces the per-level choice; it is
+// clamped to the level.
+static int z_chunk(int m, int blocks_xy, int zmax, int multiple, int req)
 {
     constexpr long long kMinBlocks = 1024;
     int zc = (int)((long long)m * blocks_xy / kMinBlocks);
     zc = zc < 1 ? 1 : (zc > zmax ? zmax : zc);
+    if (req > 0) zc = req < m ? req : m;
     return (zc + multiple - 1) / multiple * multiple;
 }
 
@@ -1198,7 +1201,7 @@ void launch_cycle_end3d(const Variant &v, const CycleEndArgs &a, hipStream_t st)
         const bool split = m >= 65 && (m - 1) % TX == 0;
         const int ntx = split ? (m - 1) / TX : (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
         const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
-        const int zc = z_chunk(m, ntx * nty + ncy, ZC, 1);
+        const int zc = z_chunk(m, ntx * nty + ncy, ZC, 1, a.zchunk);
         const dim3 grid((ntx * nty + ncy) * ((m + zc - 1) / zc)), block(kThreads);
         // Dirichlet data (the first cycle) in an instantiation of its own, so
         // that the common one has no load the compiler waits for
@@ -1224,14 +1227,14 @@ template void launch_cycle_end3d<float>(const Variant &, const CycleEndArgs &, h
 
 template <typename T>
 void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const T *sig,
-                    const double *G, unsigned long long *pres, hipStream_t st)
+                    const double *G, unsigned long long *pres, int zreq, hipStream_t st)
 {
     const int m = L.m;
     // m = 64 k + 1: k tiles of 64 columns and the last column in 4 x 128 tiles
     const bool split = m >= 65 && (m - 1) % TX == 0;
     const int ntx = split ? (m - 1) / TX : (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
     const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
-    const int zc = z_chunk(m, ntx * nty + ncy, ZC, 1);
+    const int zc = z_chunk(m, ntx * nty + ncy, ZC, 1, zreq);
     const dim3 grid((ntx * nty + ncy) * ((m + zc - 1) / zc)), block(kThreads);
     if (v.radial && v.sigma)
         hipLaunchKernelGGL((k_sweep3d<T, 1, 1>), grid, block, 0, st, ein, eout, g, sig, G, L, pres, zc, ntx, nty, ncy);
@@ -1245,7 +1248,7 @@ void launch_sweep3d(const Variant &v, const Level &L, const T *ein, T *eout, con
 
 template <typename T>
 void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, const T *g, const double *G,
-                     unsigned long long *pres, hipStream_t st)
+                     unsigned long long *pres, int zreq, hipStream_t st)
 {
     const int m = L.m;
     // m = 64 k + 1: k tiles of 64 columns and the last column in 4 x 128
@@ -1254,7 +1257,7 @@ void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, co
     const int tw = split ? TX : (m + (m + TX - 1) / TX - 1) / ((m + TX - 1) / TX);
     const int ntx = split ? (m - 1) / TX : (m + tw - 1) / tw, nty = (m + TY2 - 1) / TY2;
     const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
-    const int zt = z_chunk(m, ntx * nty + ncy, ZC2, 1);                // target z chunk
+    const int zt = z_chunk(m, ntx * nty + ncy, ZC2, 1, zreq);          // target z chunk
     const int nzc = (m + zt - 1) / zt, zc = (m + nzc - 1) / nzc;       // balanced
     const int nz = (m + zc - 1) / zc;
     const dim3 grid((ntx * nty + ncy) * nz), block(kThreads2);
@@ -1265,19 +1268,19 @@ void launch_sweep3d2(const Variant &v, const Level &L, const T *ein, T *eout, co
 }
 
 template void launch_sweep3d2<double>(const Variant &, const Level &, const double *, double *, const double *,
-                                      const double *, unsigned long long *, hipStream_t);
+                                      const double *, unsigned long long *, int, hipStream_t);
 template void launch_sweep3d2<float>(const Variant &, const Level &, const float *, float *, const float *,
-                                     const double *, unsigned long long *, hipStream_t);
+                                     const double *, unsigned long long *, int, hipStream_t);
 
 template <typename T>
-void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, hipStream_t st)
+void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first, int zreq, hipStream_t st)
 {
     const int m = 2 * mc - 1;
     // m = 64 k + 1: k tiles of 64 columns and the last column in 4 x 128 tiles
     const bool split = m >= 65 && (m - 1) % TX == 0;
     const int ntx = split ? (m - 1) / TX : (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
     const int ncy = split ? (m + kColRows - 1) / kColRows : 0;
-    const int zc = z_chunk(m, ntx * nty + ncy, ZC, 2);
+    const int zc = z_chunk(m, ntx * nty + ncy, ZC, 2, zreq);
     const dim3 grid((ntx * nty + ncy) * ((m + zc - 1) / zc)), block(kThreads);
     if (first)
         hipLaunchKernelGGL((k_prolong3d<T, true>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc, ntx, nty, ncy);
@@ -1285,23 +1288,23 @@ void launch_prolong3d(int mc, const T *ec, const T *ef_in, T *ef_out, bool first
         hipLaunchKernelGGL((k_prolong3d<T, false>), grid, block, 0, st, ec, ef_in, ef_out, mc, zc, ntx, nty, ncy);
 }
 
-template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, hipStream_t);
-template void launch_prolong3d<float>(int, const float *, const float *, float *, bool, hipStream_t);
+template void launch_prolong3d<double>(int, const double *, const double *, double *, bool, int, hipStream_t);
+template void launch_prolong3d<float>(int, const float *, const float *, float *, bool, int, hipStream_t);
 
 template <typename T>
-void launch_restrict3d(int mc, const T *fine, T *coarse, hipStream_t st)
+void launch_restrict3d(int mc, const T *fine, T *coarse, int zreq, hipStream_t st)
 {
-    const int bx = (mc + RCX - 1) / RCX, by = (mc + RCY - 1) / RCY, zc = z_chunk(mc, bx * by, ZC, 1);
+    const int bx = (mc + RCX - 1) / RCX, by = (mc + RCY - 1) / RCY, zc = z_chunk(mc, bx * by, ZC, 1, zreq);
     const dim3 grid(bx, by, (mc + zc - 1) / zc), block(kThreads);
     hipLaunchKernelGGL((k_restrict3d<T>), grid, block, 0, st, fine, coarse, mc, zc);
 }
 
-template void launch_restrict3d<double>(int, const double *, double *, hipStream_t);
-template void launch_restrict3d<float>(int, const float *, float *, hipStream_t);
+template void launch_restrict3d<double>(int, const double *, double *, int, hipStream_t);
+template void launch_restrict3d<float>(int, const float *, float *, int, hipStream_t);
 
 template void launch_sweep3d<double>(const Variant &, const Level &, const double *, double *, const double *,
-                                     const double *, const double *, unsigned long long *, hipStream_t);
+                                     const double *, const double *, unsigned long long *, int, hipStream_t);
 template void launch_sweep3d<float>(const Variant &, const Level &, const float *, float *, const float *,
-                                    const float *, const double *, unsigned long long *, hipStream_t);
+                                    const float *, const double *, unsigned long long *, int, hipStream_t);
 
 }  // namespace sgml

@@ -1,0 +1,151 @@
+"""GPU parity at the launch shapes of the full-size workloads.
+
+The benchmark workloads run kernels in shapes that small parity grids do not
+reach: the six-relaxation level-0 visit of a 4097^2 grid marches 48 (FP32)
+or 96 (FP64) rows per wavefront, and the 3D z-marching passes walk several
+planes per workgroup (4 at 129^3, up to 16 / 32 on larger levels).  These
+tests compare the library with the FP64 oracle element by element in exactly
+those shapes:
+  * one and three cycles of the 4097^2 Poisson workload itself, and its
+    converged solution against the exact discrete solution (DST-I x DCT-I);
+  * the 1025^2 cycle with the long chunks forced (chunk_rows);
+  * 3D cycles with the z chunk forced (z_chunk) at 65^3, and the 129^3 and
+    257^3 workloads with their own chunking.
+Bars: FP64 1e-12 relative L-inf; one FP32 cycle 1e-5; per-visit
+pseudo-residuals 1e-11 of their maximum.
+"""
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle.core import AXIS, RADIAL, OracleProblem
+from paper_1703_07206_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def dev(x):
+    return None if x is None else torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_problem(wl):
+    return OracleProblem(wl.dim, wl.n, wl.stencil, wl.faces, wl.a, wl.sigma)
+
+
+def gpu_plan(wl):
+    from paper_1703_07206_amd import sgml
+    return sgml.Plan(wl.dim, wl.n, wl.stencil, wl.faces, wl.a, dev(wl.sigma), precision=sgml.MIXED)
+
+
+def gpu_solve(plan, wl, precision, **kw):
+    from paper_1703_07206_amd import sgml
+    prec = sgml.MIXED if precision == "mixed" else sgml.FP64
+    u, st = plan.solve(dev(wl.f), dev(wl.G), raise_on_failure=False, precision=prec, **kw)
+    torch.cuda.synchronize()
+    return host(u), st
+
+
+def check_cycles(wl, ncyc=3, mixed=True, pres=True, **kw):
+    """One cycle (e_0 and the per-visit pseudo-residuals) and `ncyc` cycles of
+    the library against the oracle."""
+    P = oracle_problem(wl)
+    plan = gpu_plan(wl)
+    e0, pres_or = P.cycle(wl.f, G=wl.G, with_pres=True)
+    u1, st = gpu_solve(plan, wl, "fp64", tol=0.0, max_cycles=1, record_pres=pres, **kw)
+    assert st["cycles"] == 1
+    assert rel_inf(u1, e0) < 1e-12, ("1 cycle", rel_inf(u1, e0))
+    if pres:
+        err = np.max(np.abs(np.array(st["pres"]) - pres_or))
+        assert err <= 1e-11 * np.max(pres_or), err
+    if mixed:
+        m1, _ = gpu_solve(plan, wl, "mixed", tol=0.0, max_cycles=1, **kw)
+        assert rel_inf(m1, e0) < 1e-5, ("1 mixed cycle", rel_inf(m1, e0))
+    if ncyc > 1:
+        un, info = P.solve(wl.f, G=wl.G, tol=0.0, max_cycles=ncyc, stall_window=-1)
+        ug, st = gpu_solve(plan, wl, "fp64", tol=0.0, max_cycles=ncyc, stall_window=-1, **kw)
+        assert st["cycles"] == ncyc
+        assert rel_inf(ug, un) < 1e-12, (ncyc, rel_inf(ug, un))
+        assert abs(st["relres"] - info["relres"]) <= 1e-10 * info["relres"]
+
+
+# ---------------------------------------------------------------- 2D, 4097^2
+
+def test_cycles_poisson2d_blobs_4097():
+    # the benchmark workload in the benchmark's launch configuration
+    check_cycles(W.poisson2d_blobs(n=12), ncyc=3)
+
+
+def test_converged_poisson2d_blobs_4097_against_exact_solution():
+    wl = W.poisson2d_blobs(n=12)
+    ref = exact.spectral_solve(2, 12, AXIS, "DDNN", 0.0, wl.f)
+    plan = gpu_plan(wl)
+    for prec in ("fp64", "mixed"):
+        # at the benchmark's tolerance the error is bounded by ||dL^-1|| tol ||f||
+        # (1/8 for Dirichlet x-walls); driven further it meets the exact solution
+        u, st = gpu_solve(plan, wl, prec, tol=1e-12, max_cycles=100)
+        assert st["status"] == 0
+        bound = (st["relres"] * st["norm0"] / 8 + 1e-13 * np.max(np.abs(ref))) / np.max(np.abs(ref))
+        err12 = rel_inf(u, ref)
+        assert err12 <= bound, (prec, err12, bound)
+        u, st = gpu_solve(plan, wl, prec, tol=1e-14, max_cycles=100)
+        assert st["status"] == 0, st["status"]
+        err = rel_inf(u, ref)
+        print(f"4097^2 {prec}: rel-Linf vs exact {err12:.3e} at tol 1e-12, {err:.3e} at 1e-14")
+        assert err < 1e-12, (prec, err)
+
+
+# ---------------------------------------------------------------- 2D, 1025^2
+
+@pytest.mark.parametrize("chunk_rows", [0, 48, 96])
+@pytest.mark.parametrize("case", [(AXIS, "DDNN", False, 0.0), (RADIAL, "NDDN", True, -0.2)],
+                         ids=["axis-DDNN-one", "rad-NDDN-sig"])
+def test_cycles_1025_row_chunks(case, chunk_rows):
+    # the row-marching level-0 and level-1 passes with the chunk lengths of the
+    # 4097^2 launches (48 rows FP32, 96 rows FP64) forced on a 1025^2 grid
+    stencil, faces, hetero, a = case
+    wl = W.random_problem(2, 10, stencil, faces, seed=1600, hetero=hetero, a=a)
+    check_cycles(wl, ncyc=2, chunk_rows=chunk_rows)
+
+
+# ---------------------------------------------------------------- 3D
+
+Z_CASES = [
+    # stencil, faces, heterogeneous sigma, a, Dirichlet values
+    (RADIAL, "DDDDDD", False, 0.0, True),    # paired relaxation, LDS cycle end
+    (RADIAL, "NNNNDD", True, 0.0, True),     # single relaxation, Neumann lateral faces
+    (AXIS, "DNDDND", False, -0.3, False),    # paired 7-point, mixed faces
+]
+Z_IDS = ["rad-D-one", "rad-NNNNDD-sig", "axis-DNDDND-one"]
+
+
+@pytest.mark.parametrize("z_chunk", [2, 5, 16, 31, 65])
+@pytest.mark.parametrize("case", Z_CASES, ids=Z_IDS)
+def test_cycles_65_z_chunks(case, z_chunk):
+    # several planes per workgroup on 65^3: ring rotation, the march unrolled
+    # by three, chunk boundaries mid-level, one chunk for the whole level
+    stencil, faces, hetero, a, with_G = case
+    wl = W.random_problem(3, 6, stencil, faces, seed=1700, hetero=hetero, a=a, dirichlet_values=with_G)
+    check_cycles(wl, ncyc=3, z_chunk=z_chunk)
+
+
+@pytest.mark.parametrize("z_chunk", [0, 31])
+@pytest.mark.parametrize("name", ["poisson3d_charges", "helmholtz3d_spheres", "capacitor_tanh"])
+def test_cycles_129_workloads(name, z_chunk):
+    # the 3D workloads' own data at 129^3 (default chunking: 4 planes on level 0)
+    wl = W.CONFIGS[name](n=7)
+    check_cycles(wl, ncyc=2, mixed=z_chunk == 0, pres=z_chunk == 0, z_chunk=z_chunk)
+
+
+def test_cycle_helmholtz3d_spheres_257():
+    # the 257^3 workload in its own launch configuration: one cycle
+    check_cycles(W.helmholtz3d_spheres(n=8), ncyc=1)

@@ -248,6 +248,99 @@ def test_one_relaxation_amplifies_a_mode_by_closed_form_factor(dim, stencil):
     assert np.max(np.abs(u1 - amp * mode)) < 1e-13
 
 
+def _stencil_offsets(dim, stencil):
+    """Neighbour offsets d, weights w_d and prefactor C of the stencils as
+    the operator of Sec. 3 defines them: axis (5 / 7 point, w = 1, C = 1) and
+    radial (eq. 5: all 3^d - 1 neighbours, w = 1/|d|^2, C = 2d/(3^d - 1))."""
+    offs = [d for d in itertools.product((-1, 0, 1), repeat=dim) if any(d)]
+    if stencil == AXIS:
+        offs = [d for d in offs if sum(map(abs, d)) == 1]
+        return offs, [1.0] * len(offs), 1.0
+    return offs, [1.0 / sum(x * x for x in d) for d in offs], 2.0 * dim / len(offs)
+
+
+def _level_symbol(dim, stencil, p, lam_h):
+    """Eigenvalue of the sigma = 1 stride operator (spacing lam_h) on the
+    Dirichlet sine mode prod_i sin(p_i pi x_i): sum_d C w_d (prod_i cos(p_i pi
+    d_i lam_h) - 1) / lam_h^2 (the mode's neighbour values are the mode times
+    the cosines)."""
+    offs, w, C = _stencil_offsets(dim, stencil)
+    acc = 0.0
+    for d, wd in zip(offs, w):
+        acc += wd * (np.prod([np.cos(pi * np.pi * di * lam_h) for pi, di in zip(p, d)]) - 1.0)
+    return C * acc / lam_h ** 2
+
+
+@pytest.mark.parametrize("nu", [0, 1, 2])
+@pytest.mark.parametrize("dim,stencil", [(2, AXIS), (2, RADIAL), (3, AXIS), (3, RADIAL)])
+def test_relaxation_interpolation_of_a_mode_in_closed_form(dim, stencil, nu):
+    # Algorithm 2 on a sine mode with sigma = c != 1, a != 0 and a source
+    # proportional to the mode: the level-nu nodes see the stride-lam
+    # operator, whose eigenvalue on the mode is c * symbol + a, so they move
+    # by (amp - 1) mode with amp = 1 + theta (c sym + a - gamma) / D,
+    # D = c C sum_d w_d / lam_h^2 - a (the local diagonal, Sec. 2 / Sec. 3.4);
+    # every other node receives the multilinear interpolation of that
+    # variation, a product of 1D piecewise-linear interpolants of the sine
+    # (numpy.interp) over the level's nodes.
+    n = 5 if dim == 2 else 4
+    h = 1.0 / 2 ** n
+    lam = 2 ** nu
+    c, a, gamma = 2.5, -0.7, 3.0
+    p = (2, 1, 3)[:dim]
+    P = OracleProblem(dim, n, stencil, a=a, sigma=np.full((2 ** n + 1,) * dim, c))
+    x = np.linspace(0.0, 1.0, P.N)
+    grids = W.coords(n, dim)[::-1]
+    mode = np.prod([np.sin(pi * np.pi * g) for pi, g in zip(p, grids)], axis=0)
+    sym = _level_symbol(dim, stencil, p, lam * h)
+    _, w, C = _stencil_offsets(dim, stencil)
+    D = c * C * sum(w) / (lam * h) ** 2 - a
+    amp = 1.0 + P.theta * (c * sym + a - gamma) / D
+    u1, pres = P.relax_interp(nu, mode, gamma * mode, sig_nu=np.full(P.shape, c))
+    xl = x[::lam]
+    factors = [np.interp(x, xl, np.sin(pi * np.pi * xl)) for pi in p]  # per axis, x fastest
+    interp = factors[0]
+    for fct in factors[1:]:
+        interp = np.multiply.outer(fct, interp)
+    ref = mode + (amp - 1.0) * interp
+    assert np.max(np.abs(u1 - ref)) < 1e-12 * max(1.0, abs(amp))
+    # pseudo-residual: max over the level's unknowns of |(c sym + a - gamma) mode|
+    sl = tuple(slice(None, None, lam) for _ in range(dim))
+    assert abs(pres - abs(c * sym + a - gamma) * np.max(np.abs(mode[sl]))) < 1e-9 * abs(sym)
+
+
+@pytest.mark.parametrize("nu", [0, 1])
+@pytest.mark.parametrize("dim,stencil", [(2, AXIS), (2, RADIAL), (3, AXIS), (3, RADIAL)])
+def test_local_step_uses_the_face_averaged_diagonal(dim, stencil, nu):
+    # The local pseudo-time step is theta / D(x) with D the diagonal of the
+    # stride operator: C / lam_h^2 sum_d w_d (sigma(x + lam d) + sigma(x)) / 2 - a.
+    # For sigma quadratic per axis, sigma = alpha + sum_i beta_i x_i + g_i x_i^2,
+    # the odd terms cancel between d and -d and
+    #   D(x) = C / lam_h^2 (sigma(x) sum_d w_d + 1/2 sum_d w_d sum_i g_i (d_i lam_h)^2) - a,
+    # which differs from sigma(x) alone (the literal local-coefficient rule)
+    # by an O(1) term.  From u = 0 one relaxation gives u = -theta g / D(x) at
+    # the level's interior nodes.
+    n = 5 if dim == 2 else 4
+    h = 1.0 / 2 ** n
+    lam = 2 ** nu
+    a = -0.6
+    rng = np.random.default_rng(40 + dim)
+    grids = W.coords(n, dim)[::-1]
+    beta, gam = rng.uniform(-0.5, 0.5, dim), rng.uniform(0.5, 2.0, dim)
+    sigma = 1.5 + sum(b * g + q * g * g for b, q, g in zip(beta, gam, grids))
+    offs, w, C = _stencil_offsets(dim, stencil)
+    lam_h = lam * h
+    extra = 0.5 * sum(wd * sum(q * (di * lam_h) ** 2 for q, di in zip(gam, d)) for d, wd in zip(offs, w))
+    D_ref = C / lam_h ** 2 * (sigma * sum(w) + extra) - a
+    P = OracleProblem(dim, n, stencil, a=a, sigma=sigma)
+    _, D = P.apply_level(nu, np.zeros(P.shape), sig_nu=sigma, with_diag=True)
+    g = rng.uniform(-1, 1, P.shape)
+    u1, _ = P.relax_interp(nu, np.zeros(P.shape), g, sig_nu=sigma)
+    sl = tuple(slice(lam, -lam, lam) for _ in range(dim))  # interior level nodes
+    assert np.max(np.abs(D[sl] - D_ref[sl]) / D_ref[sl]) < 1e-13
+    ref = -P.theta * g[sl] / D_ref[sl]
+    assert np.max(np.abs(u1[sl] - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
 def test_dirichlet_nodes_take_the_prescribed_variation():
     n, dim = 4, 2
     P = OracleProblem(dim, n)

@@ -141,10 +141,12 @@ typedef struct {
      * kernels by class: SGML_PROF_SWEEP0 one relaxation per launch;
      * SGML_PROF_VISIT0_INJ / SGML_PROF_VISIT0 fused visits (interpolation
      * prologue, several relaxations) with / without the injection epilogue;
-     * SGML_PROF_CYCLE_END the cycle-end pass (residual recurrence) */
+     * SGML_PROF_CYCLE_END the cycle-end pass (residual recurrence).  At most
+     * 32 launches of a cycle are timed; prof_untimed counts the others. */
     int prof_launches[SGML_PROF_CLASSES];
     float prof_ms[SGML_PROF_CLASSES];
     int prof_sweeps[SGML_PROF_CLASSES];
+    int prof_untimed;
 } sgml_stats;
 
 typedef struct sgml_plan sgml_plan;

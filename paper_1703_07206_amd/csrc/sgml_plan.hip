@@ -153,6 +153,7 @@ struct sgml_plan {
     hipEvent_t ev0, ev1;
     std::vector<hipEvent_t> pev;  // profiling events, pairs around timed launches
     size_t pev_used = 0;
+    int prof_untimed = 0;         // launches of the current solve the pool could not time
     CoarseOp *ops_host;           // pinned staging of the coarse operation list
     LdsOp *lops_host;             // ... and of its LDS form
     LdsXfer *xfer_host;
@@ -220,19 +221,30 @@ double host_max(const sgml_plan *P, int t)
     return as_double(m);
 }
 
-// Profiling: a pair of events around a launch; drained once per cycle.
-// Returns the index of the pair's first event in P->pev (the pool may grow
-// while a cycle is enqueued, so callers keep indices, not pointers), or -1
-// when no event could be created.
+// Profiling: a pair of events around a launch; drained once per cycle.  The
+// pool has a fixed size, created in full before the first profiled solve
+// enqueues anything and never grown: a cycle times at most kProfPairs
+// launches, the rest run untimed (counted in the stats).
+constexpr int kProfPairs = 32;
+
+sgml_status prof_pool(sgml_plan *P)
+{
+    while (P->pev.size() < 2 * (size_t)kProfPairs) {
+        hipEvent_t e;
+        // timing only: no system-scope fence (no cache writeback) at each record
+        SGML_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+        P->pev.push_back(e);
+    }
+    return SGML_OK;
+}
+
+// Index of the next free pair's first event in P->pev, or -1 when the pool
+// is used up for this cycle.
 long prof_pair(sgml_plan *P)
 {
     if (P->pev_used + 2 > P->pev.size()) {
-        for (int t = 0; t < 64; ++t) {
-            hipEvent_t e;
-            // timing only: no system-scope fence (no cache writeback) at each record
-            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
-            P->pev.push_back(e);
-        }
+        ++P->prof_untimed;
+        return -1;
     }
     const long pr = (long)P->pev_used;
     P->pev_used += 2;
@@ -743,6 +755,11 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
     std::memset(&S, 0, sizeof(S));
     S.visits = (int)lev.size();
 
+    if (o->profile) {
+        sgml_status rc = prof_pool(P);
+        if (rc != SGML_OK) return rc;
+    }
+    P->prof_untimed = 0;
     SGML_HIP(hipEventRecord(P->ev0, st));
     clear_targets(P, 1, 1, st);
     launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), st);
@@ -859,6 +876,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
     SGML_HIP(hipEventRecord(P->ev1, st));
     SGML_HIP(hipEventSynchronize(P->ev1));
     SGML_HIP(hipEventElapsedTime(&S.ms, P->ev0, P->ev1));
+    S.prof_untimed = P->prof_untimed;
     S.status = status;
     return status;
 }
@@ -868,6 +886,29 @@ bool all_dirichlet(const sgml_plan *P)
     for (int f = 0; f < 2 * P->dim; ++f)
         if (P->prob.face[f] != SGML_DIRICHLET) return false;
     return true;
+}
+
+// Restricted coefficients per level in the plan's workspace: Algorithm 1
+// applied to sigma ("restricted sources and coefficients", Sec. 2), and their
+// FP32 copies in mixed plans.
+sgml_status build_coeff_pyramid(sgml_plan *P, hipStream_t st)
+{
+    const double *sigma = P->sigma;
+    if (!sigma) return SGML_OK;
+    const double *prev = sigma;
+    for (int nu = 1; nu < P->n; ++nu) {
+        double *cur = P->at<double>(P->lay.sig64[nu]);
+        launch_restrict<double, double>(P->dim, P->m(nu), prev, cur, st);
+        prev = cur;
+    }
+    if (P->precision == SGML_MIXED) {
+        launch_convert<double, float>(sigma, P->at<float>(P->lay.sig0t), P->M, st);
+        for (int nu = 1; nu < P->n; ++nu)
+            launch_convert<double, float>(P->at<double>(P->lay.sig64[nu]), P->at<float>(P->lay.sigt[nu]),
+                                          level_nodes(P->dim, P->n, nu), st);
+    }
+    SGML_HIP(hipGetLastError());
+    return SGML_OK;
 }
 
 }  // namespace
@@ -953,21 +994,7 @@ sgml_status sgml_plan_set_coeffs(sgml_plan *P, const double *sigma, void *stream
     P->sigma = sigma;
     P->var.sigma = sigma ? 1 : 0;
     if (!sigma) return SGML_OK;
-    // restricted coefficients per level: Algorithm 1 applied to sigma
-    const double *prev = sigma;
-    for (int nu = 1; nu < P->n; ++nu) {
-        double *cur = P->at<double>(P->lay.sig64[nu]);
-        launch_restrict<double, double>(P->dim, P->m(nu), prev, cur, st);
-        prev = cur;
-    }
-    if (P->precision == SGML_MIXED) {
-        launch_convert<double, float>(sigma, P->at<float>(P->lay.sig0t), P->M, st);
-        for (int nu = 1; nu < P->n; ++nu)
-            launch_convert<double, float>(P->at<double>(P->lay.sig64[nu]), P->at<float>(P->lay.sigt[nu]),
-                                          level_nodes(P->dim, P->n, nu), st);
-    }
-    SGML_HIP(hipGetLastError());
-    return SGML_OK;
+    return build_coeff_pyramid(P, st);
 }
 
 sgml_status sgml_solve(sgml_plan *P, const double *f, const double *G, double *u, const sgml_opts *o,

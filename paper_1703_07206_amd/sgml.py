@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
                 ("node_updates", ctypes.c_longlong), ("ms", ctypes.c_float),
                 ("prof_launches", ctypes.c_int * PROF_CLASSES),
                 ("prof_ms", ctypes.c_float * PROF_CLASSES),
-                ("prof_sweeps", ctypes.c_int * PROF_CLASSES)]
+                ("prof_sweeps", ctypes.c_int * PROF_CLASSES), ("prof_untimed", ctypes.c_int)]
 
     def as_dict(self):
         return dict(status=self.status, cycles=self.cycles, norm0=self.norm0, relres=self.relres,
@@ -54,7 +54,8 @@ class Stats(ctypes.Structure):
                     ms=self.ms,
                     prof={PROF_NAMES[c]: dict(launches=self.prof_launches[c], ms=self.prof_ms[c],
                                               sweeps=self.prof_sweeps[c])
-                          for c in range(PROF_CLASSES)})
+                          for c in range(PROF_CLASSES)},
+                    prof_untimed=self.prof_untimed)
 
 
 class SGMLError(RuntimeError):

@@ -59,6 +59,7 @@ def lib():
         L.orc_cycle.argtypes = [P(Problem), P(Opts), dp, dp, dp, dp, dp, P(Stats)]
         L.orc_solve.argtypes = [P(Problem), P(Opts), dp, dp, dp, P(Stats)]
         L.orc_coeff_grad.argtypes = [P(Problem), dp, dp, dp]
+        L.orc_adjoint.argtypes = [P(Problem), P(Opts), dp, dp, P(Stats)]
         L.orc_dirichlet_mask.argtypes = [P(Problem), dp]
         L.orc_schedule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
         _lib = L
@@ -172,6 +173,16 @@ class OracleProblem:
                     relax_updates=st.relax_updates, restrict_updates=st.restrict_updates,
                     interp_updates=st.interp_updates, fullgrid_updates=st.fullgrid_updates)
         return u, info
+
+    def adjoint(self, g, tol=1e-12, max_cycles=100, n_r=2, reading=0, stall_window=0):
+        """Solve dL^T lam = g (lam = 0 on Dirichlet nodes); returns (lam, info)."""
+        g = _f64(g)
+        lam = np.empty(self.shape)
+        st = Stats()
+        o = self._opts(tol, max_cycles, n_r, reading, stall_window)
+        rc = lib().orc_adjoint(ctypes.byref(self._p), ctypes.byref(o), _ptr(g), _ptr(lam), ctypes.byref(st))
+        assert rc != E_ARG
+        return lam, dict(status=st.status, cycles=st.cycles, relres=st.relres)
 
     def coeff_grad(self, u, lam):
         u, lam = _f64(u), _f64(lam)

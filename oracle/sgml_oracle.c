@@ -693,35 +693,74 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
     return status;
 }
 
-/* Gradient of a scalar loss with respect to the coefficient sigma, for a
- * problem whose faces are all Dirichlet, given the solution u and the
- * adjoint lambda (lambda = 0 at Dirichlet nodes).  From dL(u; sigma) = f:
- *   dLoss/dsigma_m = - sum_x lambda_x d(dL u)_x / dsigma_m
- *                  = - C/(2h^2) sum_k w_k (u_{m+d_k} - u_m)(lambda_m - lambda_{m+d_k}),
- * over neighbours inside the grid. */
+/* Trapezoid weight of a node: 1/2 for every Neumann face it lies on.  With
+ * node images on Neumann faces, the coupling of a face node to its inner
+ * neighbour is counted twice in the face node's row and once in the
+ * neighbour's, so W dL is symmetric (on the unknowns) for W = diag(weights). */
+static double trap_weight(const grid_t *g, const int c[3])
+{
+    double w = 1.0;
+    for (int ax = 0; ax < g->dim; ++ax) {
+        if (c[ax] == 0 && g->face[2 * ax] == ORC_NEUMANN) w *= 0.5;
+        if (c[ax] == g->N - 1 && g->face[2 * ax + 1] == ORC_NEUMANN) w *= 0.5;
+    }
+    return w;
+}
+
+/* Adjoint solve: dL^T lam = g on the unknowns, lam = 0 on Dirichlet nodes.
+ * Since W dL is symmetric, dL^T = W dL W^-1: lam = W mu where dL mu = W^-1 g
+ * is solved by the recurrence of Sec. 2 (orc_solve) with homogeneous
+ * conditions.  With Dirichlet faces only, W = 1 and this is the solve of g. */
+int orc_adjoint(const orc_problem *p, const orc_opts *o, const double *g, double *lam, orc_stats *st)
+{
+    if (!valid_problem(p) || !o || !g || !lam || !st) return ORC_E_ARG;
+    grid_t gr;
+    grid_init(&gr, p);
+    double *gw = malloc(sizeof(double) * (size_t)gr.M);
+    if (!gw) return ORC_E_ARG;
+    for (long long id = 0; id < gr.M; ++id) {
+        int c[3];
+        node_coords(&gr, id, c);
+        gw[id] = is_dirichlet(&gr, c) ? 0.0 : g[id] / trap_weight(&gr, c);
+    }
+    int rc = orc_solve(p, o, gw, NULL, lam, st);
+    for (long long id = 0; id < gr.M; ++id) {
+        int c[3];
+        node_coords(&gr, id, c);
+        lam[id] = is_dirichlet(&gr, c) ? 0.0 : lam[id] * trap_weight(&gr, c);
+    }
+    free(gw);
+    return rc;
+}
+
+/* Gradient of a scalar loss with respect to the coefficient sigma, given the
+ * solution u and the adjoint lam of dLoss/du (lam = 0 at Dirichlet nodes).
+ * From dL(u; sigma) = f (implicit-function theorem):
+ *   dLoss/dsigma_m = - sum_x lam_x d(dL u)_x / dsigma_m.
+ * Each term C/h^2 w_k (sigma_s + sigma_x)/2 (u_s - u_x) of row x, with s the
+ * node its neighbour k samples (an image across a Neumann face), depends on
+ * sigma_s and sigma_x with derivative C/(2h^2) w_k (u_s - u_x) each; the sum
+ * is taken literally, term by term, over the unknowns x. */
 int orc_coeff_grad(const orc_problem *p, const double *u, const double *lam, double *grad)
 {
     if (!valid_problem(p) || !u || !lam || !grad) return ORC_E_ARG;
-    for (int f = 0; f < 2 * p->dim; ++f)
-        if (p->face[f] != ORC_DIRICHLET) return ORC_E_ARG;
     grid_t g;
     grid_init(&g, p);
     double scale = g.C / (2.0 * g.h * g.h);
-#pragma omp parallel for schedule(static)
+    memset(grad, 0, sizeof(double) * (size_t)g.M);
     for (long long id = 0; id < g.M; ++id) {
         int c[3];
         node_coords(&g, id, c);
-        double acc = 0.0;
+        if (is_dirichlet(&g, c)) continue;
         for (int k = 0; k < g.K; ++k) {
-            int y[3] = {c[0] + g.off[k][0], c[1] + g.off[k][1], c[2] + g.off[k][2]};
-            int inside = 1;
-            for (int ax = 0; ax < g.dim; ++ax)
-                if (y[ax] < 0 || y[ax] > g.N - 1) inside = 0;
-            if (!inside) continue;
-            long long yid = node_index(&g, y[0], y[1], g.dim == 3 ? y[2] : 0);
-            acc += g.w[k] * (u[yid] - u[id]) * (lam[id] - lam[yid]);
+            int si = mirror(c[0] + g.off[k][0], g.N);
+            int sj = mirror(c[1] + g.off[k][1], g.N);
+            int sk = (g.dim == 3) ? mirror(c[2] + g.off[k][2], g.N) : 0;
+            long long sid = node_index(&g, si, sj, sk);
+            double d = -lam[id] * scale * g.w[k] * (u[sid] - u[id]);
+            grad[sid] += d;
+            grad[id] += d;
         }
-        grad[id] = -scale * acc;
     }
     return ORC_OK;
 }

@@ -549,6 +549,118 @@ def test_adjoint_gradients_match_finite_differences():
         assert abs(fd - gsig[node]) < 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(gsig)))
 
 
+ADJ_CASES = [(2, 4, AXIS, "DDNN"), (2, 4, RADIAL, "NDND"), (2, 3, RADIAL, "NNND"),
+             (3, 3, RADIAL, "NNNNDD"), (3, 3, AXIS, "DNDNND"), (3, 3, RADIAL, "DDDDDD")]
+
+
+def _unknown_block(A, mask):
+    un = ~mask.ravel()
+    return A[un][:, un].toarray(), un
+
+
+def _trap_weights(dim, n, faces):
+    # 1/2 per Neumann face a node lies on
+    N = 2 ** n + 1
+    w = np.ones((N,) * dim)
+    for ax in range(dim):
+        arr_ax = dim - 1 - ax
+        for side, pos in ((faces[2 * ax], 0), (faces[2 * ax + 1], N - 1)):
+            if side == "N":
+                sl = [slice(None)] * dim
+                sl[arr_ax] = pos
+                w[tuple(sl)] *= 0.5
+    return w
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", ADJ_CASES)
+def test_trapezoid_weights_symmetrise_the_operator(dim, n, stencil, faces):
+    # the reading behind the adjoint with Neumann faces: node images make dL
+    # non-symmetric, and W dL is symmetric for the trapezoid weights W
+    wl = W.random_problem(dim, n, stencil, faces, seed=50, hetero=True, a=-0.3)
+    A = exact.assemble(dim, n, stencil, faces, -0.3, wl.sigma)
+    mask = exact.dirichlet_mask(dim, n, faces)
+    Auu, un = _unknown_block(A, mask)
+    WA = _trap_weights(dim, n, faces).ravel()[un][:, None] * Auu
+    assert np.max(np.abs(WA - WA.T)) < 1e-12 * np.max(np.abs(WA))
+    if "N" in faces[:2 * dim]:
+        assert np.max(np.abs(Auu - Auu.T)) > 1e-3 * np.max(np.abs(Auu))
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", ADJ_CASES)
+def test_adjoint_is_the_transposed_solve(dim, n, stencil, faces):
+    # against a dense solve of the transposed matrix assembled independently
+    wl = W.random_problem(dim, n, stencil, faces, seed=51, hetero=True, a=-0.3)
+    P = OracleProblem(dim, n, stencil, faces, a=-0.3, sigma=wl.sigma)
+    mask = P.dirichlet_mask()
+    g = np.where(mask, 0.0, np.random.default_rng(52).uniform(-1, 1, P.shape))
+    Auu, un = _unknown_block(exact.assemble(dim, n, stencil, faces, -0.3, wl.sigma), mask)
+    ref = np.zeros(g.size)
+    ref[un] = np.linalg.solve(Auu.T, g.ravel()[un])
+    lam, info = P.adjoint(g, tol=1e-15, max_cycles=400)
+    assert info["status"] == 0
+    assert rel_inf(lam.ravel(), ref) < 1e-12
+    assert np.all(lam[mask] == 0.0)
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", ADJ_CASES)
+def test_coefficient_gradient_is_the_exact_derivative(dim, n, stencil, faces):
+    # d(lam^T dL u)/dsigma_m for any u and lam (lam = 0 on Dirichlet nodes):
+    # dL is affine in sigma, so its derivative with respect to sigma_m is the
+    # assembled matrix at sigma + e_m minus the one at sigma
+    wl = W.random_problem(dim, n, stencil, faces, seed=53, hetero=True, a=-0.3)
+    P = OracleProblem(dim, n, stencil, faces, a=-0.3, sigma=wl.sigma)
+    mask = P.dirichlet_mask()
+    rng = np.random.default_rng(54)
+    u = rng.uniform(-1, 1, P.shape)
+    lam = np.where(mask, 0.0, rng.uniform(-1, 1, P.shape))
+    grad = P.coeff_grad(u, lam)
+    A0 = exact.assemble(dim, n, stencil, faces, -0.3, wl.sigma)
+    N = P.N
+    picks = [(0,) * dim, (N - 1,) * dim, (1,) * dim, (N // 2,) * dim, (0,) + (N // 2,) * (dim - 1),
+             (N - 1,) + (1,) * (dim - 1), (N // 2,) * (dim - 1) + (N - 2,), (2,) * (dim - 1) + (0,)]
+    for m in picks:
+        sp_ = wl.sigma.copy()
+        sp_[m] += 1.0
+        B = exact.assemble(dim, n, stencil, faces, -0.3, sp_) - A0
+        ref = -(lam.ravel() @ (B @ u.ravel()))
+        assert abs(grad[m] - ref) < 1e-10 * np.max(np.abs(grad)), (m, grad[m], ref)
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", [(2, 4, RADIAL, "DDNN"), (3, 3, RADIAL, "NNNNDD")])
+def test_neumann_adjoint_gradients_match_finite_differences(dim, n, stencil, faces):
+    wl = W.random_problem(dim, n, stencil, faces, seed=55, hetero=True, a=-0.4)
+    P = OracleProblem(dim, n, stencil, faces, a=-0.4, sigma=wl.sigma)
+    m = P.dirichlet_mask()
+    ut = np.random.default_rng(56).uniform(-1, 1, P.shape)
+    u, _ = P.solve(wl.f, G=wl.G, tol=1e-15, max_cycles=400)
+    lam, _ = P.adjoint(np.where(m, 0.0, u - ut), tol=1e-15, max_cycles=400)
+    gsig = P.coeff_grad(u, lam)
+    N = P.N
+    for node in [(0,) * dim, (N // 2,) * dim, (1,) + (N - 1,) * (dim - 1), (N - 2,) * dim]:
+        if m[node]:
+            continue
+        fp, fm = wl.f.copy(), wl.f.copy()
+        fp[node] += 1.0
+        fm[node] -= 1.0
+        up, _ = P.solve(fp, G=wl.G, tol=1e-15, max_cycles=400)
+        um, _ = P.solve(fm, G=wl.G, tol=1e-15, max_cycles=400)
+        fd = (_loss(up, ut, m) - _loss(um, ut, m)) / 2.0
+        assert abs(fd - lam[node]) < 1e-8 * max(1.0, abs(fd)), (node, fd, lam[node])
+    for node in [(0,) * dim, (N - 1,) * dim, (N // 2,) * dim, (1,) * dim]:
+        d = 1e-4 * wl.sigma[node]
+        res = []
+        for sgn in (1, -1):
+            sp_ = wl.sigma.copy()
+            sp_[node] += sgn * d
+            uu, _ = OracleProblem(dim, n, stencil, faces, a=-0.4, sigma=sp_).solve(
+                wl.f, G=wl.G, tol=1e-15, max_cycles=400)
+            res.append(uu)
+        dd = np.where(m, 0.0, res[0] - res[1])
+        sm = np.where(m, 0.0, res[0] + res[1] - 2 * ut)
+        fd = 0.5 * np.sum(dd * sm) / (2 * d)
+        assert abs(fd - gsig[node]) < 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(gsig))), (node, fd, gsig[node])
+
+
 def test_cycle_is_the_golden_schedule_of_pinned_primitives():
     # Algorithm 3 composed by hand from the separately pinned pieces: the
     # visit list of tests/golden (n = 5), restriction(nu) of the source and of

@@ -123,7 +123,9 @@ def _inv(v, arr_ax, kind):
 
 
 def spectral_solve(dim, n, stencil, faces, a, f, G=None):
-    """Exact solution of dL_1 u = f (sigma = 1) with Dirichlet values G."""
+    """Exact solution of dL_1 u = f (sigma = 1) with Dirichlet values G; for
+    pure Neumann faces with a = 0 the solution of zero trapezoid mean (f must
+    then have zero trapezoid mean)."""
     N = 2 ** n + 1
     dm = dirichlet_mask(dim, n, faces)
     fa = _faces_per_axis(dim, faces)
@@ -141,7 +143,14 @@ def spectral_solve(dim, n, stencil, faces, a, f, G=None):
     v = rhs[sl].copy()
     for ax in range(dim):
         v = _fwd(v, dim - 1 - ax, fa[ax][0])
-    v = v / operator_symbol(dim, n, stencil, faces, a)
+    sym = operator_symbol(dim, n, stencil, faces, a)
+    if all(lo == "N" and hi == "N" for lo, hi in fa) and a == 0.0:
+        # pure Neumann Poisson: the constant mode (first DCT-I coefficient, the
+        # trapezoid sum) is the null space; the solution of zero mean
+        sym = sym.copy()
+        sym[(0,) * dim] = 1.0
+        v[(0,) * dim] = 0.0
+    v = v / sym
     for ax in range(dim):
         v = _inv(v, dim - 1 - ax, fa[ax][0])
     u = lift.copy()

@@ -168,6 +168,43 @@ static int is_dirichlet(const grid_t *g, const int c[3])
     return 0;
 }
 
+/* Trapezoid weight of a node: 1/2 for every Neumann face it lies on.  With
+ * node images on Neumann faces, the coupling of a face node to its inner
+ * neighbour is counted twice in the face node's row and once in the
+ * neighbour's, so W dL is symmetric (on the unknowns) for W = diag(weights). */
+static double trap_weight(const grid_t *g, const int c[3])
+{
+    double w = 1.0;
+    for (int ax = 0; ax < g->dim; ++ax) {
+        if (c[ax] == 0 && g->face[2 * ax] == ORC_NEUMANN) w *= 0.5;
+        if (c[ax] == g->N - 1 && g->face[2 * ax + 1] == ORC_NEUMANN) w *= 0.5;
+    }
+    return w;
+}
+
+static int has_dirichlet_face(const grid_t *g)
+{
+    for (int f = 0; f < 2 * g->dim; ++f)
+        if (g->face[f] == ORC_DIRICHLET) return 1;
+    return 0;
+}
+
+/* v minus its mean under the trapezoid rule (weights trap_weight): the
+ * discrete integral over the domain divided by its volume. */
+static void remove_mean(const grid_t *g, double *v)
+{
+    double sw = 0.0, swv = 0.0;
+    for (long long id = 0; id < g->M; ++id) {
+        int c[3];
+        node_coords(g, id, c);
+        double w = trap_weight(g, c);
+        sw += w;
+        swv += w * v[id];
+    }
+    double mean = swv / sw;
+    for (long long id = 0; id < g->M; ++id) v[id] -= mean;
+}
+
 static int on_level(const grid_t *g, const int c[3], int lam)
 {
     for (int ax = 0; ax < g->dim; ++ax)
@@ -618,6 +655,26 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
         ctx_free(&x);
         return ORC_E_ARG;
     }
+    /* Pure Neumann problems (no Dirichlet face; Sec. 2, last paragraph, and
+     * eq. (10)): the source must integrate to zero, so it is taken minus its
+     * mean; the trapezoid rule is the discrete integral, its weights being
+     * the ones that make W dL symmetric, so that a zero-mean source keeps the
+     * recurrence away from the constant mode (the null space for a = 0).
+     * Each cycle's correction is taken minus its mean before it is collected
+     * (the solution keeps zero mean, which fixes the shift for a = 0 and is
+     * the exact solution's mean otherwise), and the residual is re-projected
+     * against rounding. */
+    const int pure = !has_dirichlet_face(g);
+    double *fp = malloc(bytes);
+    if (!fp) {
+        free(s);
+        free(e);
+        free(Le);
+        ctx_free(&x);
+        return ORC_E_ARG;
+    }
+    memcpy(fp, f, bytes);
+    if (pure) remove_mean(g, fp);
     /* u_init and the normaliser */
     for (long long id = 0; id < g->M; ++id) {
         int c[3];
@@ -632,8 +689,8 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
         if (is_dirichlet(g, c)) {
             s[id] = 0.0;
         } else {
-            s[id] = f[id];
-            double r = fabs(f[id] - Le[id]);
+            s[id] = fp[id];
+            double r = fabs(fp[id] - Le[id]);
             if (r > norm0) norm0 = r;
         }
     }
@@ -645,15 +702,18 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
         memset(u, 0, bytes);
         for (int i = 0; i < o->max_cycles; ++i) {
             cycle_run(&x, s, i == 0 ? G : NULL, e, o, NULL, NULL, st);
+            if (pure) remove_mean(g, e);
             orc_apply(p, e, Le);
-            double rmax = 0.0;
             for (long long id = 0; id < g->M; ++id) {
                 int c[3];
                 node_coords(g, id, c);
                 u[id] += e[id];
                 s[id] = is_dirichlet(g, c) ? 0.0 : s[id] - Le[id];
-                if (!(fabs(s[id]) <= rmax)) rmax = fabs(s[id]); /* propagates NaN */
             }
+            if (pure) remove_mean(g, s);
+            double rmax = 0.0;
+            for (long long id = 0; id < g->M; ++id)
+                if (!(fabs(s[id]) <= rmax)) rmax = fabs(s[id]); /* propagates NaN */
             double rel = rmax / norm0;
             st->cycles = i + 1;
             st->relres = rel;
@@ -680,12 +740,13 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
         int c[3];
         node_coords(g, id, c);
         if (!is_dirichlet(g, c)) {
-            double r = fabs(f[id] - Le[id]);
+            double r = fabs(fp[id] - Le[id]);
             if (!(r <= tmax)) tmax = r;
         }
     }
     st->relres_true = norm0 > 0.0 ? tmax / norm0 : tmax;
     st->status = status;
+    free(fp);
     free(s);
     free(e);
     free(Le);
@@ -693,29 +754,18 @@ int orc_solve(const orc_problem *p, const orc_opts *o, const double *f, const do
     return status;
 }
 
-/* Trapezoid weight of a node: 1/2 for every Neumann face it lies on.  With
- * node images on Neumann faces, the coupling of a face node to its inner
- * neighbour is counted twice in the face node's row and once in the
- * neighbour's, so W dL is symmetric (on the unknowns) for W = diag(weights). */
-static double trap_weight(const grid_t *g, const int c[3])
-{
-    double w = 1.0;
-    for (int ax = 0; ax < g->dim; ++ax) {
-        if (c[ax] == 0 && g->face[2 * ax] == ORC_NEUMANN) w *= 0.5;
-        if (c[ax] == g->N - 1 && g->face[2 * ax + 1] == ORC_NEUMANN) w *= 0.5;
-    }
-    return w;
-}
-
 /* Adjoint solve: dL^T lam = g on the unknowns, lam = 0 on Dirichlet nodes.
  * Since W dL is symmetric, dL^T = W dL W^-1: lam = W mu where dL mu = W^-1 g
  * is solved by the recurrence of Sec. 2 (orc_solve) with homogeneous
- * conditions.  With Dirichlet faces only, W = 1 and this is the solve of g. */
+ * conditions.  With Dirichlet faces only, W = 1 and this is the solve of g.
+ * At least one face must be Dirichlet (the pure Neumann problem, solved on
+ * zero-mean sources, is not covered). */
 int orc_adjoint(const orc_problem *p, const orc_opts *o, const double *g, double *lam, orc_stats *st)
 {
     if (!valid_problem(p) || !o || !g || !lam || !st) return ORC_E_ARG;
     grid_t gr;
     grid_init(&gr, p);
+    if (!has_dirichlet_face(&gr)) return ORC_E_ARG; /* pure Neumann: not covered */
     double *gw = malloc(sizeof(double) * (size_t)gr.M);
     if (!gw) return ORC_E_ARG;
     for (long long id = 0; id < gr.M; ++id) {

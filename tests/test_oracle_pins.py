@@ -661,6 +661,41 @@ def test_neumann_adjoint_gradients_match_finite_differences(dim, n, stencil, fac
         assert abs(fd - gsig[node]) < 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(gsig))), (node, fd, gsig[node])
 
 
+def _trap_mean(v, dim, n, faces):
+    w = _trap_weights(dim, n, faces)
+    return np.sum(w * v) / np.sum(w)
+
+
+@pytest.mark.parametrize("a", [0.1, 0.0])
+@pytest.mark.parametrize("dim,n,stencil", [(2, 5, AXIS), (2, 5, RADIAL), (3, 4, RADIAL), (3, 4, AXIS)])
+def test_pure_neumann_solution_is_the_spectral_one(dim, n, stencil, a):
+    # eq. (10): lap(u) + a u = f - mean(f), zero normal derivative on every
+    # face.  Exact discrete solution by DCT-I (its first coefficient is the
+    # trapezoid sum, so the constant mode is the trapezoid mean)
+    faces = "N" * (2 * dim)
+    rng = np.random.default_rng(60 + dim)
+    f = rng.uniform(-1, 1, (2 ** n + 1,) * dim)
+    fp = f - _trap_mean(f, dim, n, faces)
+    P = OracleProblem(dim, n, stencil, faces, a=a)
+    u, info = P.solve(f, tol=1e-15, max_cycles=300)
+    assert info["status"] == 0, info["status"]
+    ref = exact.spectral_solve(dim, n, stencil, faces, a, fp)
+    assert rel_inf(u, ref) < 1e-12
+    assert abs(_trap_mean(u, dim, n, faces)) < 1e-14 * np.max(np.abs(u))
+
+
+@pytest.mark.parametrize("dim,n,stencil", [(2, 4, RADIAL), (3, 3, RADIAL)])
+def test_pure_neumann_heterogeneous_matches_dense_solve(dim, n, stencil):
+    faces = "N" * (2 * dim)
+    wl = W.random_problem(dim, n, stencil, faces, seed=62, hetero=True, a=0.1)
+    fp = wl.f - _trap_mean(wl.f, dim, n, faces)
+    P = OracleProblem(dim, n, stencil, faces, a=0.1, sigma=wl.sigma)
+    u, info = P.solve(wl.f, tol=1e-15, max_cycles=300)
+    assert info["status"] == 0
+    ref = exact.direct_solve(dim, n, stencil, faces, 0.1, fp, sigma=wl.sigma)
+    assert rel_inf(u, ref) < 1e-12
+
+
 def test_cycle_is_the_golden_schedule_of_pinned_primitives():
     # Algorithm 3 composed by hand from the separately pinned pieces: the
     # visit list of tests/golden (n = 5), restriction(nu) of the source and of

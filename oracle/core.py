@@ -12,6 +12,7 @@ import numpy as np
 from . import build as _build
 
 AXIS, RADIAL = 0, 1
+dp_t = ctypes.c_void_p
 OK, E_ARG, E_DIVERGED, E_STAGNATED, E_MAXCYCLES = 0, -1, -5, -6, -7
 
 # default pseudo-time step fractions theta (dtau = theta / D)
@@ -60,6 +61,7 @@ def lib():
         L.orc_solve.argtypes = [P(Problem), P(Opts), dp, dp, dp, P(Stats)]
         L.orc_coeff_grad.argtypes = [P(Problem), dp, dp, dp]
         L.orc_adjoint.argtypes = [P(Problem), P(Opts), dp, dp, P(Stats)]
+        L.orc_neumann_source.argtypes = [P(Problem), ctypes.POINTER(dp), dp, dp]
         L.orc_dirichlet_mask.argtypes = [P(Problem), dp]
         L.orc_schedule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
         _lib = L
@@ -183,6 +185,16 @@ class OracleProblem:
         rc = lib().orc_adjoint(ctypes.byref(self._p), ctypes.byref(o), _ptr(g), _ptr(lam), ctypes.byref(st))
         assert rc != E_ARG
         return lam, dict(status=st.status, cycles=st.cycles, relres=st.relres)
+
+    def neumann_source(self, f, flux):
+        """f minus the Neumann-data part of dL_1: flux is a sequence of 2*dim
+        face arrays (outward normal derivative, shape (N,)*(dim-1), or None)."""
+        f = _f64(f)
+        keep = [None if g is None else _f64(g) for g in (list(flux) + [None] * 6)[:6]]
+        arr = (dp_t * 6)(*[None if g is None else g.ctypes.data for g in keep])
+        out = np.empty(self.shape)
+        assert lib().orc_neumann_source(ctypes.byref(self._p), arr, _ptr(f), _ptr(out)) == OK
+        return out
 
     def coeff_grad(self, u, lam):
         u, lam = _f64(u), _f64(lam)

@@ -815,6 +815,55 @@ int orc_coeff_grad(const orc_problem *p, const double *u, const double *lam, dou
     return ORC_OK;
 }
 
+/* Neumann data (Sec. 2: the derivative is imposed at the boundary by
+ * substituting the data lying outside the domain).  flux[f] (NULL: zero)
+ * holds the outward normal derivative on Neumann face f (x-, x+, y-, y+,
+ * z-, z+) at its N^(d-1) nodes, indexed by the face's other coordinates in
+ * axis order, the lower axis fastest (x- / x+: (k N + j), y- / y+: (k N + i),
+ * z- / z+: (j N + i); 2D: j or i).  A neighbour sample that crosses a Neumann
+ * face takes the image node's value plus 2 h g at the face point (the
+ * central difference across the face), one such term for every face it
+ * crosses, g read at the image's other coordinates.  These terms do not
+ * depend on u: they are the affine part b of dL_1 at the unknowns, moved to
+ * the source, f_out = f - b, so that the solve with homogeneous images
+ * (Algorithms 1-3 unchanged) solves the problem with the Neumann data.
+ * Values at Dirichlet nodes are copied. */
+int orc_neumann_source(const orc_problem *p, const double *const flux[6], const double *f, double *f_out)
+{
+    if (!valid_problem(p) || !flux || !f || !f_out) return ORC_E_ARG;
+    grid_t g;
+    grid_init(&g, p);
+    double scale = g.C / (g.h * g.h);
+    for (long long id = 0; id < g.M; ++id) {
+        int c[3];
+        node_coords(&g, id, c);
+        f_out[id] = f[id];
+        if (is_dirichlet(&g, c)) continue;
+        double sc = p->sigma ? p->sigma[id] : 1.0;
+        double b = 0.0;
+        for (int k = 0; k < g.K; ++k) {
+            int q[3] = {c[0] + g.off[k][0], c[1] + g.off[k][1], c[2] + g.off[k][2]};
+            int s3[3] = {mirror(q[0], g.N), mirror(q[1], g.N), g.dim == 3 ? mirror(q[2], g.N) : 0};
+            double shift = 0.0;
+            for (int ax = 0; ax < g.dim; ++ax) {
+                int face = q[ax] < 0 ? 2 * ax : (q[ax] > g.N - 1 ? 2 * ax + 1 : -1);
+                if (face < 0 || g.face[face] != ORC_NEUMANN || !flux[face]) continue;
+                int t[2], nt = 0;
+                for (int bx = 0; bx < g.dim; ++bx)
+                    if (bx != ax) t[nt++] = s3[bx];
+                long long fi = nt == 2 ? (long long)t[1] * g.N + t[0] : t[0];
+                shift += 2.0 * g.h * flux[face][fi];
+            }
+            if (shift == 0.0) continue;
+            long long sid = node_index(&g, s3[0], s3[1], s3[2]);
+            double ss = p->sigma ? p->sigma[sid] : 1.0;
+            b += g.w[k] * 0.5 * (ss + sc) * shift;
+        }
+        f_out[id] = f[id] - scale * b;
+    }
+    return ORC_OK;
+}
+
 /* Node kinds: 1 for Dirichlet nodes, 0 for unknowns. */
 int orc_dirichlet_mask(const orc_problem *p, uint8_t *mask)
 {

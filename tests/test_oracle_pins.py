@@ -682,6 +682,8 @@ def test_pure_neumann_solution_is_the_spectral_one(dim, n, stencil, a):
     ref = exact.spectral_solve(dim, n, stencil, faces, a, fp)
     assert rel_inf(u, ref) < 1e-12
     assert abs(_trap_mean(u, dim, n, faces)) < 1e-14 * np.max(np.abs(u))
+    # the stop test is relative to the zero-mean source of eq. (10)
+    assert abs(info["norm0"] - np.max(np.abs(fp))) < 1e-15 * np.max(np.abs(fp))
 
 
 @pytest.mark.parametrize("dim,n,stencil", [(2, 4, RADIAL), (3, 3, RADIAL)])
@@ -694,6 +696,89 @@ def test_pure_neumann_heterogeneous_matches_dense_solve(dim, n, stencil):
     assert info["status"] == 0
     ref = exact.direct_solve(dim, n, stencil, faces, 0.1, fp, sigma=wl.sigma)
     assert rel_inf(u, ref) < 1e-12
+
+
+def _separable_quadratic(dim, n, seed):
+    """u = sum_i alpha_i x_i^2 + beta_i x_i + c, its Laplacian and the outward
+    normal derivative on every face (as face arrays in the oracle's layout)."""
+    rng = np.random.default_rng(seed)
+    al, be, c0 = rng.uniform(-1, 1, dim), rng.uniform(-1, 1, dim), rng.uniform(-1, 1)
+    grids = W.coords(n, dim)[::-1]  # x, y, (z)
+    u = c0 + sum(al[i] * grids[i] ** 2 + be[i] * grids[i] for i in range(dim))
+    lap = 2.0 * np.sum(al)
+    N = 2 ** n + 1
+    flux = []
+    for ax in range(dim):
+        # outward derivative: -du/dx_ax at x_ax = 0, +du/dx_ax at x_ax = 1
+        # (constant over the face: u is separable)
+        for side, val in ((0, -be[ax]), (1, 2 * al[ax] + be[ax])):
+            flux.append(np.full((N,) * (dim - 1), val))
+    return u, lap, flux
+
+
+@pytest.mark.parametrize("dim,n,stencil,faces", [(2, 4, AXIS, "DNNN"), (2, 4, RADIAL, "NNDN"),
+                                                 (2, 5, RADIAL, "NDNN"), (3, 3, RADIAL, "NNNNND"),
+                                                 (3, 3, AXIS, "NNDNNN"), (3, 4, RADIAL, "NDNNNN")])
+def test_neumann_data_reproduce_a_quadratic(dim, n, stencil, faces):
+    # A separable quadratic with its Laplacian as the source, its values on the
+    # Dirichlet face and its outward derivative on the Neumann faces: both
+    # stencils are exact on it, and so is the central difference across a face
+    # that the data substitute, so the discrete solution is the quadratic.
+    a = -0.4
+    u, lap, flux = _separable_quadratic(dim, n, seed=70 + n)
+    f = lap + a * u
+    P = OracleProblem(dim, n, stencil, faces, a=a)
+    fn = P.neumann_source(f, flux)
+    m = P.dirichlet_mask()
+    # the homogeneous-image operator reproduces the shifted source ...
+    h = 1.0 / 2 ** n
+    assert np.max(np.abs(np.where(m, 0.0, P.apply(u) - fn))) < 1e-11 / h ** 2
+    # ... and the solve with the data returns the quadratic
+    us, info = P.solve(fn, G=u, tol=1e-15, max_cycles=300)
+    assert info["status"] == 0
+    assert rel_inf(us, u) < 1e-12
+    # faces without data are homogeneous; Dirichlet faces ignore data
+    assert np.array_equal(P.neumann_source(f, [None] * 6), f)
+
+
+@pytest.mark.parametrize("dim,stencil,faces", [(2, AXIS, "DNNN"), (2, RADIAL, "NNDD"),
+                                              (3, AXIS, "NNNNDN"), (3, RADIAL, "NNDDDD")])
+def test_neumann_data_varying_along_the_face(dim, stencil, faces):
+    # u = x^2 y (2D), x^2 y + y^2 z + z^2 x (3D): cubic, but every stencil term
+    # is exact on it (second differences of at most quadratic profiles, mixed
+    # differences of linear ones), and each monomial is at most quadratic in
+    # the normal direction, so the face difference is exact as well.  Its
+    # normal derivative varies along the faces, which checks the layout of the
+    # face arrays.  (Radial diagonals that cross two Neumann faces read the
+    # data at mirrored coordinates, which is exact only for data constant
+    # near the corner: the radial cases keep their Neumann faces apart.)
+    n = 4
+    N = 2 ** n + 1
+    grids = W.coords(n, dim)[::-1]
+    x1 = np.linspace(0.0, 1.0, N)
+    if dim == 2:
+        X, Y = grids
+        u = X ** 2 * Y
+        f = 2 * Y
+        # face arrays indexed by the other coordinate
+        flux = [np.zeros(N), np.full(N, 0.0) + 2 * x1, -x1 ** 2, x1 ** 2]
+        # x- : -u_x(0, y) = 0;  x+ : u_x(1, y) = 2y;  y- : -u_y(x, 0) = -x^2;  y+ : u_y(x, 1) = x^2
+    else:
+        X, Y, Z = grids
+        u = X ** 2 * Y + Y ** 2 * Z + Z ** 2 * X
+        f = 2 * Y + 2 * Z + 2 * X
+        B, A = np.meshgrid(x1, x1, indexing="ij")  # (slow, fast) face coordinates
+        # x faces: index (z, y) -> A = y, B = z;  u_x = 2 x y + z^2
+        # y faces: index (z, x) -> A = x, B = z;  u_y = x^2 + 2 y z
+        # z faces: index (y, x) -> A = x, B = y;  u_z = y^2 + 2 z x
+        flux = [-(B ** 2), 2 * A + B ** 2, -(A ** 2), A ** 2 + 2 * B, -(B ** 2), B ** 2 + 2 * A]
+    a = -0.3
+    f = f + a * u
+    P = OracleProblem(dim, n, stencil, faces, a=a)
+    fn = P.neumann_source(f, flux)
+    us, info = P.solve(fn, G=u, tol=1e-15, max_cycles=300)
+    assert info["status"] == 0
+    assert rel_inf(us, u) < 1e-12
 
 
 def test_cycle_is_the_golden_schedule_of_pinned_primitives():

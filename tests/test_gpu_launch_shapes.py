@@ -55,6 +55,23 @@ def gpu_solve(plan, wl, precision, **kw):
     return host(u), st
 
 
+def pres_bar(wl, pres_or, state):
+    """Bar for FP64 pseudo-residuals |dL_lam u - g| evaluated in two orders:
+    1e-11 of their maximum, plus the rounding of a neighbour-sum evaluation,
+    8 eps D max|u| with D = C/h^2 sum_k w_k the level-0 diagonal (the oracle
+    subtracts the centre value per neighbour first; the library's constant-
+    coefficient relaxations form scale * sum(neighbours) + (a - D) u_c - g, two
+    terms of size D |u| that cancel, whose rounding grows as 1/h^2: at 4097^2
+    it exceeds the first term)."""
+    h = 1.0 / 2 ** wl.n
+    K = 2 * wl.dim if wl.stencil == AXIS else 3 ** wl.dim - 1
+    C = 1.0 if wl.stencil == AXIS else 2.0 * wl.dim / K
+    sw = 2 * wl.dim if wl.stencil == AXIS else (4 + 2.0 if wl.dim == 2 else 6 + 6.0 + 8 / 3)
+    smax = 1.0 if wl.sigma is None else float(np.max(wl.sigma))
+    D = C * sw * smax / h ** 2
+    return 1e-11 * np.max(pres_or) + 8 * np.finfo(float).eps * D * np.max(np.abs(state))
+
+
 def check_cycles(wl, ncyc=3, mixed=True, pres=True, **kw):
     """One cycle (e_0 and the per-visit pseudo-residuals) and `ncyc` cycles of
     the library against the oracle."""
@@ -66,7 +83,7 @@ def check_cycles(wl, ncyc=3, mixed=True, pres=True, **kw):
     assert rel_inf(u1, e0) < 1e-12, ("1 cycle", rel_inf(u1, e0))
     if pres:
         err = np.max(np.abs(np.array(st["pres"]) - pres_or))
-        assert err <= 1e-11 * np.max(pres_or), err
+        assert err <= pres_bar(wl, pres_or, e0), (err, pres_bar(wl, pres_or, e0))
     if mixed:
         m1, _ = gpu_solve(plan, wl, "mixed", tol=0.0, max_cycles=1, **kw)
         assert rel_inf(m1, e0) < 1e-5, ("1 mixed cycle", rel_inf(m1, e0))

@@ -159,7 +159,10 @@ size_t sgml_workspace_bytes(const sgml_problem *prob, int precision);
 /* Create a plan: validates prob (SGML_E_ARG / SGML_E_SHAPE), checks that
  * `workspace` (device, ws_bytes long, 256-byte aligned) holds at least
  * sgml_workspace_bytes(prob, precision) (SGML_E_WORKSPACE), and records the
- * current device.  The plan uses sigma = 1 until sgml_plan_set_coeffs. */
+ * current device.  The plan uses sigma = 1 until sgml_plan_set_coeffs.
+ * workspace NULL with ws_bytes 0 creates a plan without workspace, which only
+ * sgml_solve_noalloc and sgml_coeff_grad accept (the others return
+ * SGML_E_WORKSPACE). */
 sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *workspace,
                              size_t ws_bytes, sgml_plan **out);
 
@@ -181,6 +184,31 @@ sgml_status sgml_plan_set_coeffs(sgml_plan *plan, const double *sigma, void *str
  * test). */
 sgml_status sgml_solve(sgml_plan *plan, const double *f, const double *G, double *u,
                        const sgml_opts *opts, void *stream, sgml_stats *stats);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): sgml_solve with a
+ * static workspace the library holds on each device in place of the plan's.
+ *   - The static workspace is SGML_NOALLOC_WORKSPACE_BYTES (64 MiB) per
+ *     device, reserved when the library's code is loaded on the device and
+ *     held until the process ends; sgml_workspace_bytes(prob, precision)
+ *     must not exceed it (2D up to 1025^2 in either precision, 3D up to
+ *     65^3, and 129^3 in FP64 plans), else SGML_E_WORKSPACE and nothing is
+ *     enqueued.
+ *   - plan may have been created with a workspace or without one
+ *     (sgml_plan_create with workspace NULL and ws_bytes 0, a plan only this
+ *     entry point can solve with).  The plan's own workspace is not touched.
+ *   - The call allocates nothing: no device, pinned or managed memory, no
+ *     events (opts->profile must be 0, else SGML_E_ARG); the coefficient
+ *     pyramid of the plan's sigma is rebuilt in the static workspace on every
+ *     call, since the previous call on the device may have been another plan's.
+ *   - Every call on a device shares that device's workspace: calls that
+ *     overlap in time on one device (other host threads, other streams) race
+ *     and give wrong results.  Calls ordered on one stream, or separated by
+ *     synchronisation, are safe.
+ * Other arguments, results and statuses as sgml_solve. */
+#define SGML_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+sgml_status sgml_solve_noalloc(sgml_plan *plan, const double *f, const double *G, double *u,
+                               const sgml_opts *opts, void *stream, sgml_stats *stats);
 
 /* Residual of a candidate solution (Sec. 2 recurrence, Sec. 3.1 norm):
  *   r = f - dL(u) at unknowns, 0 at Dirichlet nodes (r: device N^d or NULL);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -911,6 +912,33 @@ sgml_status build_coeff_pyramid(sgml_plan *P, hipStream_t st)
     return SGML_OK;
 }
 
+// Workspace for sgml_solve_noalloc: one array per device, kept by the
+// device's copy of the code object until the process ends.  Host code never
+// names it (in host code the name is a host-side stand-in, not a device
+// address); it uses the device address looked up once per device.
+constexpr size_t kScratchBytes = SGML_NOALLOC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex scratch_lock;
+void *scratch_ptr[kMaxDevices];  // device address of `scratch` per device, null until looked up
+
+// Look up the current device's `scratch` (once per device).  Returns null
+// when the lookup fails.
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> guard(scratch_lock);
+    if (!scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_ptr[device] = ptr;
+    }
+    return scratch_ptr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -931,7 +959,10 @@ sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *work
     if (precision != SGML_FP64 && precision != SGML_MIXED) return SGML_E_ARG;
     if (!valid_shape(prob)) return SGML_E_SHAPE;
     const Layout lay = make_layout(prob, precision);
-    if (!workspace || ws_bytes < lay.total || ((uintptr_t)workspace % kAlign) != 0) return SGML_E_WORKSPACE;
+    // no workspace at all: a plan for sgml_solve_noalloc only
+    const bool no_ws = !workspace && ws_bytes == 0;
+    if (!no_ws && (!workspace || ws_bytes < lay.total || ((uintptr_t)workspace % kAlign) != 0))
+        return SGML_E_WORKSPACE;
     sgml_plan *P = new (std::nothrow) sgml_plan();
     if (!P) return SGML_E_ARG;
     P->prob = *prob;
@@ -954,7 +985,9 @@ sgml_status sgml_plan_create(const sgml_problem *prob, int precision, void *work
     P->ws_bytes = ws_bytes;
     P->lay = lay;
     P->sigma = nullptr;
-    if (hipGetDevice(&P->device) != hipSuccess ||
+    // set-up of the device's static workspace (sgml_solve_noalloc) happens here,
+    // once per device, so that the no-allocation entry point never triggers it
+    if (hipGetDevice(&P->device) != hipSuccess || !scratch_of(P->device) ||
         hipHostMalloc((void **)&P->host, sizeof(unsigned long long) * kScalars, hipHostMallocDefault) !=
             hipSuccess) {
         delete P;
@@ -993,7 +1026,7 @@ sgml_status sgml_plan_set_coeffs(sgml_plan *P, const double *sigma, void *stream
     SGML_HIP(hipSetDevice(P->device));
     P->sigma = sigma;
     P->var.sigma = sigma ? 1 : 0;
-    if (!sigma) return SGML_OK;
+    if (!sigma || !P->ws) return SGML_OK;  // a plan without workspace builds it per solve
     return build_coeff_pyramid(P, st);
 }
 
@@ -1006,6 +1039,7 @@ sgml_status sgml_solve(sgml_plan *P, const double *f, const double *G, double *u
     if (o->precision == SGML_MIXED && P->precision != SGML_MIXED) return SGML_E_WORKSPACE;
     if (o->schedule != SGML_SCHEDULE_ONCE && o->schedule != SGML_SCHEDULE_EACH) return SGML_E_ARG;
     if (u == f || (G && u == G)) return SGML_E_ARG;
+    if (!P->ws) return SGML_E_WORKSPACE;
     SGML_HIP(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
     sgml_status rc = o->precision == SGML_MIXED ? run_solve<float>(P, f, G, u, o, st, stats)
@@ -1014,10 +1048,40 @@ sgml_status sgml_solve(sgml_plan *P, const double *f, const double *G, double *u
     return rc;
 }
 
+sgml_status sgml_solve_noalloc(sgml_plan *P, const double *f, const double *G, double *u, const sgml_opts *o,
+                               void *stream, sgml_stats *stats)
+{
+    if (!P || !f || !u || !o) return SGML_E_ARG;
+    if (o->max_cycles < 1 || !(o->tol >= 0.0)) return SGML_E_ARG;
+    if (o->precision != SGML_FP64 && o->precision != SGML_MIXED) return SGML_E_ARG;
+    if (o->precision == SGML_MIXED && P->precision != SGML_MIXED) return SGML_E_WORKSPACE;
+    if (o->schedule != SGML_SCHEDULE_ONCE && o->schedule != SGML_SCHEDULE_EACH) return SGML_E_ARG;
+    if (o->profile) return SGML_E_ARG;  // profiling creates events
+    if (u == f || (G && u == G)) return SGML_E_ARG;
+    if (P->lay.total > kScratchBytes) return SGML_E_WORKSPACE;  // beyond the static workspace
+    SGML_HIP(hipSetDevice(P->device));
+    void *ptr = scratch_ptr[P->device];  // looked up when the plan was created
+    if (!ptr) return SGML_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    // the static workspace stands in for the plan's own for this call; other
+    // calls on the device may have left anything there, so the coefficient
+    // pyramid is rebuilt (every other region is initialised by the solve)
+    char *own = P->ws;
+    P->ws = static_cast<char *>(ptr);
+    sgml_status rc = build_coeff_pyramid(P, st);
+    if (rc == SGML_OK)
+        rc = o->precision == SGML_MIXED ? run_solve<float>(P, f, G, u, o, st, stats)
+                                        : run_solve<double>(P, f, G, u, o, st, stats);
+    P->ws = own;
+    if (stats) stats->status = rc;
+    return rc;
+}
+
 sgml_status sgml_residual(sgml_plan *P, const double *f, const double *G, const double *u, double *r,
                           double *rmax, double *norm0, void *stream)
 {
     if (!P || !f || !u) return SGML_E_ARG;
+    if (!P->ws) return SGML_E_WORKSPACE;
     SGML_HIP(hipSetDevice(P->device));
     hipStream_t st = (hipStream_t)stream;
     clear_targets(P, 1, 2, st);

@@ -80,6 +80,7 @@ def lib():
         L.sgml_plan_create.argtypes = [P(Problem), ctypes.c_int, vp, ctypes.c_size_t, P(vp)]
         L.sgml_plan_set_coeffs.argtypes = [vp, vp, vp]
         L.sgml_solve.argtypes = [vp, vp, vp, vp, P(Opts), vp, P(Stats)]
+        L.sgml_solve_noalloc.argtypes = [vp, vp, vp, vp, P(Opts), vp, P(Stats)]
         L.sgml_residual.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_double), P(ctypes.c_double), vp]
         L.sgml_adjoint.argtypes = [vp, vp, vp, P(Opts), vp, P(Stats)]
         L.sgml_coeff_grad.argtypes = [vp, vp, vp, vp, vp]
@@ -89,7 +90,7 @@ def lib():
         L.sgml_status_string.argtypes = [ctypes.c_int]
         L.sgml_plan_destroy.argtypes = [vp]
         L.sgml_plan_destroy.restype = None
-        for name in ("sgml_plan_create", "sgml_plan_set_coeffs", "sgml_solve", "sgml_residual",
+        for name in ("sgml_plan_create", "sgml_plan_set_coeffs", "sgml_solve", "sgml_solve_noalloc", "sgml_residual",
                      "sgml_adjoint", "sgml_coeff_grad", "sgml_schedule"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -146,10 +147,12 @@ class Plan:
     for x-, x+, y-, y+, z-, z+, ``a`` the constant of L = div(sigma grad) + a,
     ``sigma`` an optional (N,)*dim float64 CUDA tensor, ``precision`` the
     highest precision mode the plan will be asked for (MIXED covers both).
+    ``workspace=False`` creates a plan without a device workspace, which only
+    ``solve_noalloc`` (and ``coeff_grad``) can use.
     """
 
     def __init__(self, dim, n, stencil=AXIS, faces="DDDDDD", a=0.0, sigma=None, precision=FP64,
-                 theta=0.0, device=None):
+                 theta=0.0, device=None, workspace=True):
         L = lib()
         self.dim, self.n = dim, n
         self.N = 2 ** n + 1
@@ -161,11 +164,13 @@ class Plan:
         nbytes = L.sgml_workspace_bytes(ctypes.byref(self._prob), precision)
         if nbytes == 0:
             raise SGMLError(E_ARG, "sgml_workspace_bytes")
+        self.workspace_bytes = nbytes
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device) if workspace else None
             h = ctypes.c_void_p()
-            rc = L.sgml_plan_create(ctypes.byref(self._prob), precision, self.workspace.data_ptr(),
-                                    nbytes, ctypes.byref(h))
+            rc = L.sgml_plan_create(ctypes.byref(self._prob), precision,
+                                    self.workspace.data_ptr() if workspace else None,
+                                    nbytes if workspace else 0, ctypes.byref(h))
         if rc != OK:
             raise SGMLError(rc, "sgml_plan_create")
         self._h = h
@@ -208,6 +213,22 @@ class Plan:
                               ctypes.byref(st))
         if rc in (E_ARG, E_SHAPE, E_WORKSPACE, E_HIP, E_UNSUPPORTED) or (rc != OK and raise_on_failure):
             raise SGMLError(rc, "sgml_solve")
+        return u, st.as_dict()
+
+    def solve_noalloc(self, f, G=None, u=None, raise_on_failure=True, stream=None, **kw):
+        """``solve`` through sgml_solve_noalloc: the library's static per-device
+        workspace instead of the plan's; ``u`` should be given by callers that
+        cannot allocate (else it is allocated here, by torch)."""
+        self._check(f, "f")
+        self._check(G, "G")
+        if u is None:
+            u = torch.empty_like(f)
+        o = self.opts(**kw)
+        st = Stats()
+        rc = lib().sgml_solve_noalloc(self._h, _ptr(f), _ptr(G), _ptr(u), ctypes.byref(o), _stream(stream),
+                                      ctypes.byref(st))
+        if rc in (E_ARG, E_SHAPE, E_WORKSPACE, E_HIP, E_UNSUPPORTED) or (rc != OK and raise_on_failure):
+            raise SGMLError(rc, "sgml_solve_noalloc")
         return u, st.as_dict()
 
     def residual(self, f, u, G=None, r=None, stream=None):

@@ -68,7 +68,7 @@ def test_status_strings_and_argument_errors():
     prob = sg.make_problem(2, 5)
     h = ctypes.c_void_p()
     # no workspace / misaligned workspace are rejected before any device call
-    assert L.sgml_plan_create(ctypes.byref(prob), 0, None, 0, ctypes.byref(h)) == sg.E_WORKSPACE
+    assert L.sgml_plan_create(ctypes.byref(prob), 0, None, 1 << 20, ctypes.byref(h)) == sg.E_WORKSPACE
     assert L.sgml_plan_create(ctypes.byref(prob), 0, 16, 1 << 30, ctypes.byref(h)) == sg.E_WORKSPACE
     assert L.sgml_plan_create(ctypes.byref(prob), 5, None, 0, ctypes.byref(h)) == sg.E_ARG
     bad = sg.make_problem(2, 1)

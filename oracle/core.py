@@ -11,12 +11,13 @@ import numpy as np
 
 from . import build as _build
 
-AXIS, RADIAL = 0, 1
+AXIS, RADIAL, RADIAL_PRINTED = 0, 1, 2
 dp_t = ctypes.c_void_p
 OK, E_ARG, E_DIVERGED, E_STAGNATED, E_MAXCYCLES = 0, -1, -5, -6, -7
 
 # default pseudo-time step fractions theta (dtau = theta / D)
-DEFAULT_THETA = {(AXIS, 2): 0.8, (AXIS, 3): 6.0 / 7.0, (RADIAL, 2): 1.0, (RADIAL, 3): 1.0}
+DEFAULT_THETA = {(AXIS, 2): 0.8, (AXIS, 3): 6.0 / 7.0, (RADIAL, 2): 1.0, (RADIAL, 3): 1.0,
+                 (RADIAL_PRINTED, 2): 1.0, (RADIAL_PRINTED, 3): 1.0}
 
 
 class Problem(ctypes.Structure):

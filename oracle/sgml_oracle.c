@@ -36,6 +36,7 @@
 #define ORC_NEUMANN 1
 #define ORC_AXIS 0
 #define ORC_RADIAL 1
+#define ORC_RADIAL_PRINTED 2
 
 enum {
     ORC_OK = 0,
@@ -48,7 +49,7 @@ enum {
 typedef struct {
     int dim;              /* 2 or 3 */
     int n;                /* N = 2^n + 1 nodes per axis, h = 1 / 2^n */
-    int stencil;          /* ORC_AXIS or ORC_RADIAL */
+    int stencil;          /* ORC_AXIS, ORC_RADIAL or ORC_RADIAL_PRINTED */
     int face[6];          /* ORC_DIRICHLET / ORC_NEUMANN, x-, x+, y-, y+, z-, z+ */
     double a;             /* constant of L = div(sigma grad) + a */
     double theta;         /* pseudo-time step as a fraction of 1/diagonal */
@@ -100,7 +101,9 @@ typedef struct {
  * the squared distance (h l)^2 -- a first difference over h*l is a radial
  * derivative; the flux integral adds the second factor 1/(h l).  With this
  * reading the stencil reproduces the Laplacian of quadratics exactly and
- * its forward-Euler limit is the paper's dtau < h^2/2 (Sec. 2). */
+ * its forward-Euler limit is the paper's dtau < h^2/2 (Sec. 2).
+ * ORC_RADIAL_PRINTED keeps eq. (5) as printed, one factor 1/(h l) per term
+ * (weights 1/l, same prefactor); it exists to measure the discrepancy. */
 static void grid_init(grid_t *g, const orc_problem *p)
 {
     g->dim = p->dim;
@@ -122,7 +125,8 @@ static void grid_init(grid_t *g, const orc_problem *p)
                 g->off[g->K][0] = dx;
                 g->off[g->K][1] = dy;
                 g->off[g->K][2] = dz;
-                g->w[g->K] = (p->stencil == ORC_AXIS) ? 1.0 : 1.0 / (double)nz;
+                g->w[g->K] = (p->stencil == ORC_AXIS) ? 1.0
+                             : (p->stencil == ORC_RADIAL) ? 1.0 / (double)nz : 1.0 / sqrt((double)nz);
                 g->K++;
             }
     g->C = (p->stencil == ORC_AXIS) ? 1.0 : (2.0 * p->dim) / (double)g->K;
@@ -446,7 +450,7 @@ static int valid_problem(const orc_problem *p)
     if (!p) return 0;
     if (p->dim != 2 && p->dim != 3) return 0;
     if (p->n < 1 || p->n > 14) return 0;
-    if (p->stencil != ORC_AXIS && p->stencil != ORC_RADIAL) return 0;
+    if (p->stencil != ORC_AXIS && p->stencil != ORC_RADIAL && p->stencil != ORC_RADIAL_PRINTED) return 0;
     for (int f = 0; f < 2 * p->dim; ++f)
         if (p->face[f] != ORC_DIRICHLET && p->face[f] != ORC_NEUMANN) return 0;
     if (!(p->theta > 0.0)) return 0;

@@ -15,7 +15,7 @@ import pytest
 import scipy.linalg as sla
 
 from oracle import exact
-from oracle.core import AXIS, RADIAL, OracleProblem, schedule
+from oracle.core import AXIS, RADIAL, RADIAL_PRINTED, OracleProblem, schedule
 from paper_1703_07206_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -137,6 +137,49 @@ def test_radial_stencil_forward_euler_limit_is_papers_bound():
             Lm = OracleProblem(dim, n, stencil).apply(mode)
             rq = np.sum(Lm * mode) / np.sum(mode * mode) * h ** 2
             assert abs(rq - limit) < 0.02 * abs(limit), (dim, stencil, rq)
+
+
+@pytest.mark.parametrize("dim,ratio", [(2, (1 + np.sqrt(2)) / 2), (3, (3 / 13) * (2 + 8 / np.sqrt(2) + 8 / np.sqrt(3)) / 2)])
+def test_printed_radial_weights_scale_the_laplacian(dim, ratio):
+    # eq. (5) as printed (one factor 1/(h l) per term): on u = x^2 it gives
+    # ratio * lap(u) instead of lap(u), ratio = C sum_d w_d d_x^2 / 2 with
+    # w = 1/l: (1 + sqrt 2)/2 = 1.2071 in 2D, 1.4164 in 3D (the 1/l^2 reading
+    # gives 1)
+    n = 4
+    grids = W.coords(n, dim)[::-1]
+    u = grids[0] ** 2
+    sl = tuple(slice(1, -1) for _ in range(dim))
+    got = OracleProblem(dim, n, RADIAL_PRINTED).apply(u)[sl]
+    assert np.max(np.abs(got - 2.0 * ratio)) < 1e-9
+    ok = OracleProblem(dim, n, RADIAL).apply(u)[sl]
+    assert np.max(np.abs(ok - 2.0)) < 1e-9
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_printed_radial_weights_break_the_papers_step(dim):
+    # At the pseudo-time step the paper states, dtau = h^2 / 2 (Sec. 2), the
+    # 1/l^2 stencil sits at the forward-Euler limit (|amplification| <= 1 on
+    # every mode; -0.995 on the mode below), the printed 1/l stencil beyond it:
+    # the mode sin((N-2) pi x) sin(pi y) (sin(pi z)) grows by -1.41 (2D) and
+    # -1.82 (3D) per relaxation, so the paper's step diverges with it.
+    n = 5
+    h = 1.0 / 2 ** n
+    N = 2 ** n + 1
+    grids = W.coords(n, dim)[::-1]
+    p = (N - 2,) + (1,) * (dim - 1)
+    mode = np.prod([np.sin(pi * np.pi * g) for pi, g in zip(p, grids)], axis=0)
+    c = tuple([N // 2 + 1] * dim)
+    amps = {}
+    for st in (RADIAL, RADIAL_PRINTED):
+        offs = [d for d in itertools.product((-1, 0, 1), repeat=dim) if any(d)]
+        w = [1 / sum(x * x for x in d) if st == RADIAL else 1 / np.sqrt(sum(x * x for x in d)) for d in offs]
+        C = 2.0 * dim / len(offs)
+        theta = (h * h / 2) * C * sum(w) / h ** 2  # dtau = theta / D = h^2 / 2
+        P = OracleProblem(dim, n, st, theta=theta)
+        u1, _ = P.relax_interp(0, mode, np.zeros(P.shape))
+        amps[st] = u1[c] / mode[c]
+    assert abs(amps[RADIAL]) <= 1.0
+    assert abs(amps[RADIAL_PRINTED]) > 1.3
 
 
 # --------------------------------------------------------------- restriction

@@ -18,8 +18,14 @@
  *     sits at (i h, j h, k h), h = 2^-n.  Boundary nodes are included.
  *   - Faces are ordered x-, x+, y-, y+, z-, z+.  A node on any Dirichlet face
  *     is a Dirichlet node (it carries no equation); every other node is an
- *     unknown.  Neumann faces are homogeneous (zero normal derivative) and
- *     are imposed by node images (Sec. 2: reflection about the face).
+ *     unknown.  Neumann faces are imposed by node images (Sec. 2: reflection
+ *     about the face); their solves are homogeneous, and Neumann data enter
+ *     through the source (sgml_neumann_source).
+ *   - With no Dirichlet face at all (the pure Neumann problem of Sec. 3.2,
+ *     eq. (10)) the source is taken minus its mean and the solution has zero
+ *     mean (Sec. 2, last paragraph): means are trapezoid-rule means (weight
+ *     1/2 per face a node lies on), the discrete integral under which the
+ *     operator with node images is symmetric.
  *   - "device" pointers are HIP device memory of the device that is current
  *     when the plan is created; "host" pointers are ordinary host memory.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
@@ -220,19 +226,43 @@ sgml_status sgml_residual(sgml_plan *plan, const double *f, const double *G, con
                           double *r, double *rmax, double *norm0, void *stream);
 
 /* Adjoint solve dL^T(lambda) = g on the unknowns with lambda = 0 on
- * Dirichlet nodes.  For all-Dirichlet faces the operator is symmetric and
- * this is sgml_solve with source g and zero Dirichlet values.  Other faces:
- * SGML_E_UNSUPPORTED.  g, lambda: device N^d. */
+ * Dirichlet nodes (the transposed system of the implicit-function theorem
+ * on dL(u) = f).  For all-Dirichlet faces the operator is symmetric and this
+ * is sgml_solve with source g and zero Dirichlet values.  With Neumann faces
+ * the node images make dL symmetric only under the trapezoid weights W (1/2
+ * per Neumann face a node lies on), dL^T = W dL W^-1: the library solves
+ * dL mu = W^-1 g with the same cycle and returns lambda = W mu.  With no
+ * Dirichlet face at all: SGML_E_UNSUPPORTED.  g, lambda: device N^d (lambda
+ * may not alias g). */
 sgml_status sgml_adjoint(sgml_plan *plan, const double *g, double *lambda, const sgml_opts *opts,
                          void *stream, sgml_stats *stats);
 
-/* Gradient of a loss with respect to sigma (all-Dirichlet faces only),
- * given the solution u and the adjoint lambda of dLoss/du:
+/* Gradient of a loss with respect to sigma, given the solution u and the
+ * adjoint lambda of dLoss/du (implicit-function theorem on dL(u) = f):
+ *   grad[m] = -sum_x lambda[x] d(dL u)[x] / dsigma[m],
+ * every stencil term C/h^2 w_k (sigma_s + sigma_x)/2 (u_s - u_x) of row x
+ * (s the node neighbour k samples, an image across a Neumann face)
+ * contributing to sigma_s and sigma_x.  For all-Dirichlet faces
  *   grad[m] = -C/(2h^2) sum_k w_k (u[m+d_k] - u[m]) (lambda[m] - lambda[m+d_k])
- * over neighbours inside the grid (implicit-function theorem on dL(u) = f).
- * u, lambda, grad: device N^d. */
+ * over neighbours inside the grid.  u, lambda, grad: device N^d. */
 sgml_status sgml_coeff_grad(sgml_plan *plan, const double *u, const double *lambda, double *grad,
                             void *stream);
+
+/* Neumann data (Sec. 2: the derivative at the boundary imposed by substituting
+ * the data lying outside the domain).  flux[f] (f = x-, x+, y-, y+, z-, z+;
+ * host array of 6 device pointers, entries of Dirichlet faces and of faces
+ * beyond the dimension ignored, NULL = zero) holds the outward normal
+ * derivative on face f at its N^(d-1) nodes, indexed by the face's other
+ * coordinates in axis order, the lower axis fastest: x faces (k N + j), y
+ * faces (k N + i), z faces (j N + i); in 2D j, resp. i.  A neighbour sample
+ * that crosses a Neumann face takes the image's value plus 2 h g (the
+ * central difference across the face), one term per face crossed, g read at
+ * the image's other coordinates.  These terms do not depend on u: this call
+ * writes f_out = f - (their part of dL) at the unknowns (f elsewhere), and
+ * sgml_solve(f_out) then solves the problem with the Neumann data.  f, f_out:
+ * device N^d (may alias). */
+sgml_status sgml_neumann_source(sgml_plan *plan, const double *f, const double *const *flux, double *f_out,
+                                void *stream);
 
 /* Visit list of Algorithm 3 for N = 2^n + 1: level[v], count[v] for
  * v < min(*len, cap); *len receives the full length.  Host only. */

@@ -200,9 +200,33 @@ void launch_boundary(const Variant &v, const Level &L, const T *e, double escale
                      const double *sigma, double *u, double *s, T *shat, double shat_scale,
                      unsigned long long *norm, hipStream_t st);
 
+// wscale: the source is W^-1 f, W the trapezoid weights (1/2 per Neumann
+// face a node lies on), as the transposed solve needs.
 void launch_init(const Variant &v, const Level &L, const double *f, const double *G,
                  const double *sigma, double *s, double *u, unsigned long long *norm0,
-                 hipStream_t st);
+                 bool wscale, hipStream_t st);
+// u = W u at every node.
+void launch_trap_scale(const Level &L, int dim, double *u, hipStream_t st);
+
+// Pure Neumann problems: *mean = scale * (trapezoid mean of v), summed in a
+// fixed order through `partial` (wsum_partials(dim, m) doubles); then
+// s -= *mean_s, u -= *mean_e (mean_e may be null), shat = s * shat_scale (shat
+// may be null) and norm = max |s|.
+size_t wsum_partials(int dim, int m);
+template <typename T>
+void launch_wmean(int dim, const Level &L, const T *v, double scale, double *partial, double *mean,
+                  hipStream_t st);
+template <typename T>
+void launch_project(int dim, const Level &L, double *s, double *u, const double *mean_s, const double *mean_e,
+                    T *shat, double shat_scale, unsigned long long *norm, hipStream_t st);
+
+// Neumann data per face (outward normal derivative, N^(d-1) values each, or
+// null for zero), moved to the source: out = f - (flux part of dL_1).
+struct FaceData {
+    const double *g[6];
+};
+void launch_neumann_source(const Variant &v, const Level &L, const double *f, const FaceData &flux,
+                           const double *sigma, double h, double *out, hipStream_t st);
 
 template <typename T>
 void launch_source_cast(const Level &L, int dim, const double *s, T *shat, double scale,

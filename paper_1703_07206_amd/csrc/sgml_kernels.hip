@@ -21,6 +21,7 @@
 #include "sgml_device.h"
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <type_traits>
 #include <utility>
@@ -618,9 +619,28 @@ __global__ __launch_bounds__(256) void k_boundary(const T *__restrict__ E, doubl
     block_max(rb, norm);
 }
 
+// Trapezoid weight of node (i, j, k): 1/2 for every Neumann face (a face not
+// in dir) it lies on.  W dL is symmetric under the node images of Neumann
+// faces, so dL^T = W dL W^-1.
+template <int DIM>
+__device__ __forceinline__ double trap_weight(int i, int j, int k, int m, unsigned dir)
+{
+    double w = 1.0;
+    if (i == 0 && !(dir & 1u)) w *= 0.5;
+    if (i == m - 1 && !(dir & 2u)) w *= 0.5;
+    if (j == 0 && !(dir & 4u)) w *= 0.5;
+    if (j == m - 1 && !(dir & 8u)) w *= 0.5;
+    if (DIM == 3) {
+        if (k == 0 && !(dir & 16u)) w *= 0.5;
+        if (k == m - 1 && !(dir & 32u)) w *= 0.5;
+    }
+    return w;
+}
+
 // Start of a solve: u = 0, s = f at unknowns (0 at Dirichlet nodes), and
 // norm0 = max |f - dL_1 u_init| with u_init = G on Dirichlet nodes, 0 else.
-template <int DIM, int RAD, int SIG>
+// WS: the source is W^-1 f (first step of the transposed solve).
+template <int DIM, int RAD, int SIG, bool WS>
 __global__ __launch_bounds__(256) void k_init(const double *__restrict__ f, const double *__restrict__ G,
                                               const double *__restrict__ sigma, double *__restrict__ s,
                                               double *__restrict__ u, Level L,
@@ -639,11 +659,21 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ f, cons
                 return (G && is_dir<DIM>(a, b, d, m, L.dir)) ? G[lin(a, b, d, m)] : 0.0;
             };
             const double Lb = stencil_full<DIM, RAD, SIG>(val, sigma, i, j, k, m, L.dir, L.scale, L.a);
-            s[c] = f[c];
-            rb = dbits(f[c] - Lb);
+            const double fc = WS ? f[c] / trap_weight<DIM>(i, j, k, m, L.dir) : f[c];
+            s[c] = fc;
+            rb = dbits(fc - Lb);
         }
     }
     block_max(rb, norm0);
+}
+
+// u = W u (last step of the transposed solve).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_trap_scale(double *__restrict__ u, Level L)
+{
+    int i, j, k;
+    if (!node_of<DIM>(L.m, i, j, k)) return;
+    u[lin(i, j, k, L.m)] *= trap_weight<DIM>(i, j, k, L.m, L.dir);
 }
 
 template <typename T, int DIM>
@@ -700,8 +730,15 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ f, 
     block_max(nb, norm0);
 }
 
-// dLoss/dsigma_m = -scale/2 sum_k w_k (u_k - u_m)(lam_m - lam_k), in-grid
-// neighbours only (all faces Dirichlet).
+// dLoss/dsigma_m = -sum_x lam_x d(dL u)_x / dsigma_m (lam = 0 on Dirichlet
+// nodes).  Row x holds scale w_k (sigma_s + sigma_x)/2 (u_s - u_x) for each
+// neighbour k, s the node it samples (an image across a Neumann face), so
+// sigma_m enters
+//   (a) its own row:  scale/2 sum_k w_k (u_s(m,k) - u_m), times lam_m;
+//   (b) every row x whose neighbour k samples m:  scale/2 w_k (u_m - u_x),
+//       times lam_x.  x + d_k is then m itself or one of m's images (per
+//       axis -1 for m = 1, m for m = m - 2: the positions that reflect onto m).
+// Nodes of Dirichlet faces have lam = 0, so their rows drop out by themselves.
 template <int DIM, int RAD>
 __global__ __launch_bounds__(256) void k_coeff_grad(const double *__restrict__ u,
                                                     const double *__restrict__ lam,
@@ -712,6 +749,140 @@ __global__ __launch_bounds__(256) void k_coeff_grad(const double *__restrict__ u
     if (!node_of<DIM>(m, i, j, k)) return;
     const size_t c = lin(i, j, k, m);
     const double uc = u[c], lc = lam[c];
+    // positions reflecting onto this node, per axis (the node itself first)
+    int px[3], py[3], pz[3], nx = 0, ny = 0, nz = 0;
+    auto images = [&](int v, int *p, int &np) {
+        p[np++] = v;
+        if (v == 1) p[np++] = -1;
+        if (v == m - 2) p[np++] = m;
+    };
+    images(i, px, nx);
+    images(j, py, ny);
+    if (DIM == 3) images(k, pz, nz);
+    else pz[nz++] = 0;
+    double own[3] = {0.0, 0.0, 0.0}, oth[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+                if (cls == 0 || (!RAD && cls != 1)) continue;
+                // (a) the node's own row
+                const size_t q = lin(mir(i + dx, m), mir(j + dy, m), DIM == 3 ? mir(k + dz, m) : 0, m);
+                own[cls - 1] += u[q] - uc;
+                // (b) rows x = p - d over the images p of the node
+                for (int a = 0; a < nz; ++a)
+                    for (int b = 0; b < ny; ++b)
+                        for (int e = 0; e < nx; ++e) {
+                            const int xi = px[e] - dx, xj = py[b] - dy, xk = pz[a] - dz;
+                            if (xi < 0 || xi >= m || xj < 0 || xj >= m) continue;
+                            if (DIM == 3 && (xk < 0 || xk >= m)) continue;
+                            const size_t x = lin(xi, xj, DIM == 3 ? xk : 0, m);
+                            oth[cls - 1] += lam[x] * (uc - u[x]);
+                        }
+            }
+        }
+    }
+    const double third = 1.0 / 3.0;
+    const double sa = own[0] + 0.5 * own[1] + third * own[2];
+    const double sb = oth[0] + 0.5 * oth[1] + third * oth[2];
+    grad[c] = -0.5 * L.scale * (lc * sa + sb);
+}
+
+// ------------------------------------------------- pure Neumann problems
+
+// Trapezoid-weighted sums, in a fixed order (so that a solve stays bitwise
+// reproducible): each block sums kSumChunk consecutive nodes (thread t the
+// nodes t, t + 256, ...; then a tree over the block) into partial[block];
+// k_wmean_finish adds the partials the same way and divides by the total
+// weight.
+constexpr int kSumThreads = 256, kSumPerThread = 16, kSumChunk = kSumThreads * kSumPerThread;
+
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double part[kSumThreads];
+    part[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    return part[0];
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kSumThreads) void k_wsum(const T *__restrict__ v, Level L,
+                                                      double *__restrict__ partial)
+{
+    const int m = L.m;
+    const long long total = DIM == 3 ? (long long)m * m * m : (long long)m * m;
+    const long long base = (long long)blockIdx.x * kSumChunk;
+    double acc = 0.0;
+    for (int q = 0; q < kSumPerThread; ++q) {
+        const long long id = base + q * kSumThreads + threadIdx.x;
+        if (id >= total) break;
+        const int i = (int)(id % m), j = (int)((id / m) % m), k = DIM == 3 ? (int)(id / ((long long)m * m)) : 0;
+        acc += trap_weight<DIM>(i, j, k, m, L.dir) * (double)v[id];
+    }
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_wmean_finish(const double *__restrict__ partial, int nparts,
+                                                              double scale, double weight,
+                                                              double *__restrict__ mean)
+{
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += kSumThreads) acc += partial[q];
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) *mean = scale * b / weight;
+}
+
+// s -= mean_s; u -= mean_e (when given); shat = s * shat_scale (when given);
+// norm = max |s|.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_project(double *__restrict__ s, double *__restrict__ u,
+                                                 const double *__restrict__ mean_s,
+                                                 const double *__restrict__ mean_e, T *__restrict__ shat,
+                                                 double shat_scale, Level L, unsigned long long *__restrict__ norm)
+{
+    int i, j, k;
+    unsigned long long rb = 0;
+    const int m = L.m;
+    if (node_of<DIM>(m, i, j, k)) {
+        const size_t c = lin(i, j, k, m);
+        const double sn = s[c] - *mean_s;
+        s[c] = sn;
+        if (mean_e) u[c] -= *mean_e;
+        if (shat) shat[c] = (T)(sn * shat_scale);
+        rb = dbits(sn);
+    }
+    block_max(rb, norm);
+}
+
+// Neumann data moved to the source: f_out = f - b at unknowns (f elsewhere),
+// b the part of dL_1 the flux contributes through the values substituted
+// outside the domain: a neighbour sample crossing Neumann face f takes the
+// image's value plus 2 h g_f, g_f read on the face at the image's other
+// coordinates (x faces indexed (k N + j), y faces (k N + i), z faces
+// (j N + i); 2D: j or i).
+template <int DIM, int RAD, int SIG>
+__global__ __launch_bounds__(256) void k_neumann_source(const double *__restrict__ f, FaceData flux,
+                                                        const double *__restrict__ sigma, double h,
+                                                        double *__restrict__ out, Level L)
+{
+    int i, j, k;
+    const int m = L.m;
+    if (!node_of<DIM>(m, i, j, k)) return;
+    const size_t c = lin(i, j, k, m);
+    if (is_dir<DIM>(i, j, k, m, L.dir)) {
+        out[c] = f[c];
+        return;
+    }
+    const double sc = SIG ? sigma[c] : 1.0;
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
@@ -721,15 +892,25 @@ __global__ __launch_bounds__(256) void k_coeff_grad(const double *__restrict__ u
             for (int dx = -1; dx <= 1; ++dx) {
                 const int cls = (dx != 0) + (dy != 0) + (dz != 0);
                 if (cls == 0 || (!RAD && cls != 1)) continue;
-                const int ii = i + dx, jj = j + dy, kk = k + dz;
-                if (ii < 0 || ii >= m || jj < 0 || jj >= m) continue;
-                if (DIM == 3 && (kk < 0 || kk >= m)) continue;
-                const size_t q = lin(ii, jj, DIM == 3 ? kk : 0, m);
-                acc[cls - 1] += (u[q] - uc) * (lc - lam[q]);
+                const int qi = i + dx, qj = j + dy, qk = k + dz;
+                const int si = mir(qi, m), sj = mir(qj, m), sk = DIM == 3 ? mir(qk, m) : 0;
+                double shift = 0.0;
+                // faces crossed: x (index by image's (k, j)), y ((k, i)), z ((j, i))
+                if (qi < 0 && flux.g[0]) shift += flux.g[0][(size_t)sk * m + sj];
+                if (qi > m - 1 && flux.g[1]) shift += flux.g[1][(size_t)sk * m + sj];
+                if (qj < 0 && flux.g[2]) shift += flux.g[2][(size_t)sk * m + si];
+                if (qj > m - 1 && flux.g[3]) shift += flux.g[3][(size_t)sk * m + si];
+                if (DIM == 3) {
+                    if (qk < 0 && flux.g[4]) shift += flux.g[4][(size_t)sj * m + si];
+                    if (qk > m - 1 && flux.g[5]) shift += flux.g[5][(size_t)sj * m + si];
+                }
+                if (shift == 0.0) continue;
+                const double ss = SIG ? sigma[lin(si, sj, sk, m)] : 1.0;
+                acc[cls - 1] += 0.5 * (ss + sc) * 2.0 * h * shift;
             }
         }
     }
-    grad[c] = -0.5 * L.scale * (acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2]);
+    out[c] = f[c] - L.scale * (acc[0] + 0.5 * acc[1] + (1.0 / 3.0) * acc[2]);
 }
 
 // ----------------------------------------------------------- dispatch glue
@@ -912,10 +1093,14 @@ struct BoundaryRun {
 template <int D, int R, int S>
 struct InitRun {
     static void run(const Level &L, const double *f, const double *G, const double *sigma, double *s,
-                    double *u, unsigned long long *norm0, hipStream_t st)
+                    double *u, unsigned long long *norm0, bool wscale, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_init<D, R, S>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, s, u, L,
-                           norm0);
+        if (wscale)
+            hipLaunchKernelGGL((k_init<D, R, S, true>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, s, u,
+                               L, norm0);
+        else
+            hipLaunchKernelGGL((k_init<D, R, S, false>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, s,
+                               u, L, norm0);
     }
 };
 template <int D, int R, int S>
@@ -939,9 +1124,17 @@ void launch_boundary(const Variant &v, const Level &L, const T *e, double escale
 }
 
 void launch_init(const Variant &v, const Level &L, const double *f, const double *G, const double *sigma,
-                 double *s, double *u, unsigned long long *norm0, hipStream_t st)
+                 double *s, double *u, unsigned long long *norm0, bool wscale, hipStream_t st)
 {
-    dispatch3<InitRun>(v, L, f, G, sigma, s, u, norm0, st);
+    dispatch3<InitRun>(v, L, f, G, sigma, s, u, norm0, wscale, st);
+}
+
+void launch_trap_scale(const Level &L, int dim, double *u, hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_trap_scale<2>), grid_of(2, L.m), block_of(), 0, st, u, L);
+    else
+        hipLaunchKernelGGL((k_trap_scale<3>), grid_of(3, L.m), block_of(), 0, st, u, L);
 }
 
 template <typename T>
@@ -980,6 +1173,62 @@ void launch_coeff_grad(const Variant &v, const Level &L, const double *u, const 
     else
         hipLaunchKernelGGL((k_coeff_grad<3, 1>), grid_of(3, L.m), block_of(), 0, st, u, lam, grad, L);
 }
+
+size_t wsum_partials(int dim, int m)
+{
+    const size_t total = dim == 3 ? (size_t)m * m * m : (size_t)m * m;
+    return (total + kSumChunk - 1) / kSumChunk;
+}
+
+template <typename T>
+void launch_wmean(int dim, const Level &L, const T *v, double scale, double *partial, double *mean,
+                  hipStream_t st)
+{
+    const int nparts = (int)wsum_partials(dim, L.m);
+    const double weight = std::pow((double)(L.m - 1), dim);  // total trapezoid weight, all faces Neumann
+    if (dim == 2)
+        hipLaunchKernelGGL((k_wsum<T, 2>), dim3(nparts), dim3(kSumThreads), 0, st, v, L, partial);
+    else
+        hipLaunchKernelGGL((k_wsum<T, 3>), dim3(nparts), dim3(kSumThreads), 0, st, v, L, partial);
+    hipLaunchKernelGGL(k_wmean_finish, dim3(1), dim3(kSumThreads), 0, st, partial, nparts, scale, weight, mean);
+}
+
+template <typename T>
+void launch_project(int dim, const Level &L, double *s, double *u, const double *mean_s, const double *mean_e,
+                    T *shat, double shat_scale, unsigned long long *norm, hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL((k_project<T, 2>), grid_of(2, L.m), block_of(), 0, st, s, u, mean_s, mean_e, shat,
+                           shat_scale, L, norm);
+    else
+        hipLaunchKernelGGL((k_project<T, 3>), grid_of(3, L.m), block_of(), 0, st, s, u, mean_s, mean_e, shat,
+                           shat_scale, L, norm);
+}
+
+namespace {
+template <int D, int R, int S>
+struct NeumannSourceRun {
+    static void run(const Level &L, const double *f, const FaceData &flux, const double *sigma, double h,
+                    double *out, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_neumann_source<D, R, S>), grid_of(D, L.m), block_of(), 0, st, f, flux, sigma, h,
+                           out, L);
+    }
+};
+}  // namespace
+
+void launch_neumann_source(const Variant &v, const Level &L, const double *f, const FaceData &flux,
+                           const double *sigma, double h, double *out, hipStream_t st)
+{
+    dispatch3<NeumannSourceRun>(v, L, f, flux, sigma, h, out, st);
+}
+
+template void launch_wmean<double>(int, const Level &, const double *, double, double *, double *, hipStream_t);
+template void launch_wmean<float>(int, const Level &, const float *, double, double *, double *, hipStream_t);
+template void launch_project<double>(int, const Level &, double *, double *, const double *, const double *,
+                                     double *, double, unsigned long long *, hipStream_t);
+template void launch_project<float>(int, const Level &, double *, double *, const double *, const double *,
+                                    float *, double, unsigned long long *, hipStream_t);
 
 // explicit instantiations
 template void launch_fill<double>(double *, size_t, double, hipStream_t);

@@ -31,7 +31,7 @@ constexpr int kDefaultCoarseNodes = 5000;
 constexpr int kDefaultFuseMin = 129;  // smallest 2D level (nodes per axis) visited in one fused pass
 
 struct Layout {
-    size_t scal, ops, lops, xfer, levels, s, s2, e0, shat, sig0t;
+    size_t scal, ops, lops, xfer, levels, s, s2, e0, shat, sig0t, part, means;
     size_t e[kMaxLevels][2], g[kMaxLevels], sig64[kMaxLevels], sigt[kMaxLevels];
     size_t total;
 };
@@ -75,6 +75,9 @@ Layout make_layout(const sgml_problem *p, int precision)
     L.lops = take(sizeof(LdsOp) * kMaxCoarseOps);
     L.xfer = take(sizeof(LdsXfer) * kMaxXfers);
     L.levels = take(sizeof(Level) * kMaxLevels);
+    // trapezoid-mean partial sums and the two means of a pure Neumann solve
+    L.part = take(sizeof(double) * wsum_partials(p->dim, (1 << p->n) + 1));
+    L.means = take(sizeof(double) * 2);
     L.s = take(8 * M);
     L.e0 = take(2 * 8 * M);  // two level-0 buffers, FP64-sized (FP32 uses half)
     L.shat = mixed ? take(4 * M) : 0;
@@ -738,9 +741,11 @@ int coarse_level_of(const sgml_plan *P, int coarse_nodes)
     return nu;
 }
 
+// wscale: the source is W^-1 f and the result is W times the solution (the
+// transposed solve, dL^T = W dL W^-1 under the node images of Neumann faces).
 template <typename T>
 sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u, const sgml_opts *o,
-                      hipStream_t st, sgml_stats *stats)
+                      hipStream_t st, sgml_stats *stats, bool wscale = false)
 {
     const bool mixed = sizeof(T) == 4;
     const Level L0 = P->level(0);
@@ -763,7 +768,16 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
     P->prof_untimed = 0;
     SGML_HIP(hipEventRecord(P->ev0, st));
     clear_targets(P, 1, 1, st);
-    launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), st);
+    launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), wscale, st);
+    // pure Neumann (Sec. 2, last paragraph; eq. (10)): the source minus its
+    // trapezoid mean; norm0 is that of the projected source
+    const bool pure = P->dir == 0;
+    double *part = P->at<double>(P->lay.part), *means = P->at<double>(P->lay.means);
+    if (pure) {
+        launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
+        clear_targets(P, 1, 1, st);
+        launch_project<double>(P->dim, L0, s, u, means, nullptr, (double *)nullptr, 0.0, target(P, 1), st);
+    }
     SGML_HIP(hipGetLastError());
     sgml_status rc = fetch(P, 1, 1, st);
     if (rc != SGML_OK) return rc;
@@ -777,8 +791,10 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
     } else {
         std::vector<HostOp> ops;
         long long updates_per_cycle = 0;
-        const bool z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N);
-        const bool row_march = P->dim == 2 && o->fuse >= 0 && P->N >= 64;
+        // the fused cycle ends also write the next cycle's source, which a pure
+        // Neumann solve re-projects: it takes the generic cycle end
+        const bool z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N) && !pure;
+        const bool row_march = P->dim == 2 && o->fuse >= 0 && P->N >= 64 && !pure;
         // the 2D row-marching cycle end of the mixed cycle also restricts the
         // new source to level 1; it then writes the residual to the other buffer
         T *g1 = mixed && row_march && P->n >= 2 ? P->at<T>(P->lay.g[1]) : nullptr;
@@ -808,6 +824,8 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             const int k_next = mixed ? std::ilogb(last) : 0;
             const long ev = o->profile ? prof_pair(P) : -1;
             if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
+            // pure Neumann: the cycle's correction is collected minus its mean
+            if (pure) launch_wmean<T>(P->dim, L0, e, std::ldexp(1.0, k_cur), part, means + 1, st);
             if (row_march || z_march) {
                 CycleEndArgs ca;
                 ca.e = e;
@@ -835,6 +853,14 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             if (ev >= 0) {
                 SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
                 timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
+            }
+            if (pure) {
+                // s - dL(e - mean e) = s - dL e + a mean e differs from s - dL e by a
+                // constant, which the projection of the residual removes
+                launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
+                clear_targets(P, 0, 1, st);
+                launch_project<T>(P->dim, L0, s, u, means, means + 1, shat, std::ldexp(1.0, -k_next), target(P, 0),
+                                  st);
             }
             SGML_HIP(hipGetLastError());
             rc = fetch(P, 0, 1, st);
@@ -874,6 +900,7 @@ sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u,
             for (size_t v = 0; v < lev.size(); ++v) S.pres[v] = host_max(P, kPres + (int)v);
         }
     }
+    if (wscale) launch_trap_scale(L0, P->dim, u, st);
     SGML_HIP(hipEventRecord(P->ev1, st));
     SGML_HIP(hipEventSynchronize(P->ev1));
     SGML_HIP(hipEventElapsedTime(&S.ms, P->ev0, P->ev1));
@@ -1098,16 +1125,45 @@ sgml_status sgml_adjoint(sgml_plan *P, const double *g, double *lambda, const sg
                          sgml_stats *stats)
 {
     if (!P) return SGML_E_ARG;
-    if (!all_dirichlet(P)) return SGML_E_UNSUPPORTED;
-    // symmetric operator: the transposed solve is the solve itself, with the
-    // adjoint vanishing on Dirichlet nodes
-    return sgml_solve(P, g, nullptr, lambda, o, stream, stats);
+    if (all_dirichlet(P)) {
+        // symmetric operator: the transposed solve is the solve itself, with
+        // the adjoint vanishing on Dirichlet nodes
+        return sgml_solve(P, g, nullptr, lambda, o, stream, stats);
+    }
+    if (P->dir == 0) return SGML_E_UNSUPPORTED;  // pure Neumann: not covered
+    // W dL is symmetric for the trapezoid weights W (node images of Neumann
+    // faces): lambda = W mu with dL mu = W^-1 g
+    if (!P || !g || !lambda || !o) return SGML_E_ARG;
+    if (o->max_cycles < 1 || !(o->tol >= 0.0)) return SGML_E_ARG;
+    if (o->precision != SGML_FP64 && o->precision != SGML_MIXED) return SGML_E_ARG;
+    if (o->precision == SGML_MIXED && P->precision != SGML_MIXED) return SGML_E_WORKSPACE;
+    if (o->schedule != SGML_SCHEDULE_ONCE && o->schedule != SGML_SCHEDULE_EACH) return SGML_E_ARG;
+    if (lambda == g) return SGML_E_ARG;
+    if (!P->ws) return SGML_E_WORKSPACE;
+    SGML_HIP(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    sgml_status rc = o->precision == SGML_MIXED ? run_solve<float>(P, g, nullptr, lambda, o, st, stats, true)
+                                                : run_solve<double>(P, g, nullptr, lambda, o, st, stats, true);
+    if (stats) stats->status = rc;
+    return rc;
+}
+
+sgml_status sgml_neumann_source(sgml_plan *P, const double *f, const double *const *flux, double *f_out,
+                                void *stream)
+{
+    if (!P || !f || !flux || !f_out) return SGML_E_ARG;
+    SGML_HIP(hipSetDevice(P->device));
+    FaceData fd;
+    for (int q = 0; q < 6; ++q)
+        fd.g[q] = (q < 2 * P->dim && !(P->dir & (1u << q))) ? flux[q] : nullptr;
+    launch_neumann_source(P->var, P->level(0), f, fd, P->sigma, P->h, f_out, (hipStream_t)stream);
+    SGML_HIP(hipGetLastError());
+    return SGML_OK;
 }
 
 sgml_status sgml_coeff_grad(sgml_plan *P, const double *u, const double *lambda, double *grad, void *stream)
 {
     if (!P || !u || !lambda || !grad) return SGML_E_ARG;
-    if (!all_dirichlet(P)) return SGML_E_UNSUPPORTED;
     SGML_HIP(hipSetDevice(P->device));
     launch_coeff_grad(P->var, P->level(0), u, lambda, grad, (hipStream_t)stream);
     SGML_HIP(hipGetLastError());

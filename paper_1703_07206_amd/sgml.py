@@ -84,6 +84,7 @@ def lib():
         L.sgml_residual.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_double), P(ctypes.c_double), vp]
         L.sgml_adjoint.argtypes = [vp, vp, vp, P(Opts), vp, P(Stats)]
         L.sgml_coeff_grad.argtypes = [vp, vp, vp, vp, vp]
+        L.sgml_neumann_source.argtypes = [vp, vp, vp, vp, vp]
         L.sgml_schedule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int,
                                     P(ctypes.c_int)]
         L.sgml_status_string.restype = ctypes.c_char_p
@@ -91,7 +92,7 @@ def lib():
         L.sgml_plan_destroy.argtypes = [vp]
         L.sgml_plan_destroy.restype = None
         for name in ("sgml_plan_create", "sgml_plan_set_coeffs", "sgml_solve", "sgml_solve_noalloc", "sgml_residual",
-                     "sgml_adjoint", "sgml_coeff_grad", "sgml_schedule"):
+                     "sgml_adjoint", "sgml_coeff_grad", "sgml_neumann_source", "sgml_schedule"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -250,6 +251,22 @@ class Plan:
         if rc in (E_ARG, E_SHAPE, E_WORKSPACE, E_HIP, E_UNSUPPORTED) or (rc != OK and raise_on_failure):
             raise SGMLError(rc, "sgml_adjoint")
         return lam, st.as_dict()
+
+    def neumann_source(self, f, flux, out=None, stream=None):
+        """f minus the Neumann-data part of dL (sgml_neumann_source): flux is a
+        sequence of up to 6 face tensors (outward normal derivative, shape
+        (N,)*(dim-1), float64 on the device) or None."""
+        if out is None:
+            out = torch.empty_like(f)
+        faces = list(flux) + [None] * (6 - len(flux))
+        for g in faces:
+            if g is not None and tuple(g.shape) != (self.N,) * (self.dim - 1):
+                raise ValueError(f"face data of shape {tuple(g.shape)}, expected {(self.N,) * (self.dim - 1)}")
+        arr = (ctypes.c_void_p * 6)(*[_ptr(g) for g in faces])
+        rc = lib().sgml_neumann_source(self._h, _ptr(f), ctypes.addressof(arr), _ptr(out), _stream(stream))
+        if rc != OK:
+            raise SGMLError(rc, "sgml_neumann_source")
+        return out
 
     def coeff_grad(self, u, lam, grad=None, stream=None):
         if grad is None:

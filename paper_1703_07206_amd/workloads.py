@@ -21,6 +21,9 @@ Helmholtz-Poisson examples):
 ``helmholtz3d_adjoint`` 129^3, same medium, f = U(-1,1), loss target u_t
 ``poisson3d_charges``   513^3, radial 27-point, Dirichlet 0, 256 Gaussian
                      point charges of width 2h plus 1e-3 U(-1,1) noise
+``neumann_circle``   65^2 / 129^2, the grid-deformation potential of Sec. 3.2:
+                     a = 0.1, zero normal derivative on every face, a delta source
+                     on a circle built from tensor hats
 ``capacitor_tanh``   129^3, the heterogeneous Laplace problem of Sec. 3.4:
                      sigma = 0.55 +/- 0.45 tanh((r - 0.2)/0.1) (eq. 16), u = +1 on
                      the top and -1 on the bottom face, Neumann lateral faces
@@ -55,6 +58,22 @@ class Workload:
         return self.N ** self.dim
 
 
+def dirichlet_mask(dim, n, faces):
+    """Boolean array of the nodes on Dirichlet faces (faces: 'D'/'N' for
+    x-, x+, y-, y+, z-, z+), in array order."""
+    N = 2 ** n + 1
+    m = np.zeros((N,) * dim, bool)
+    faces = (faces + "DDDDDD")[:6]
+    for ax in range(dim):
+        arr_ax = dim - 1 - ax
+        for side, pos in ((faces[2 * ax], 0), (faces[2 * ax + 1], N - 1)):
+            if side == "D":
+                sl = [slice(None)] * dim
+                sl[arr_ax] = pos
+                m[tuple(sl)] = True
+    return m
+
+
 def coords(n, dim):
     """Node coordinates x_i = i h, returned in array order (z, y, x)."""
     N = 2 ** n + 1
@@ -69,6 +88,17 @@ def poisson2d_sine(n=7, seed=1, noise=0.1):
     Y, X = coords(n, 2)
     f = 2.0 * np.pi ** 2 * np.sin(np.pi * X) * np.sin(np.pi * Y) + noise * eta
     return Workload("poisson2d_sine", 2, n, AXIS, "DDDD", 0.0, -f)
+
+
+def manufactured2d(n=10):
+    """Sec. 3.1: lap(u) = f on the unit square, u = 0 on the boundary, with the
+    closed-form solution u = -x^2 y^2 (1 - x^2)(1 - y^2) (eq. 7) and its source
+    (eq. 8); 5-point stencil.  The exact continuous solution is returned in
+    extra["u_exact"].  No random draws."""
+    Y, X = coords(n, 2)
+    u = -X ** 2 * Y ** 2 * (1 - X ** 2) * (1 - Y ** 2)
+    f = -2.0 * (Y ** 2 * (1 - 6 * X ** 2) * (1 - Y ** 2) + X ** 2 * (1 - 6 * Y ** 2) * (1 - X ** 2))
+    return Workload("manufactured2d", 2, n, AXIS, "DDDD", 0.0, f, extra=dict(u_exact=u))
 
 
 def _blobs2d(n, centers, widths, amps):
@@ -132,13 +162,16 @@ def helmholtz3d_spheres(n=8, seed=3, k=0.5):
 
 
 def smooth_target(n, rng, modes=8):
-    """u_t = sum_j b_j prod_i sin(m_ji pi x_i), m in {1,2,3}, b ~ U(-1,1)."""
+    """u_t = sum_j b_j prod_i sin(m_ji pi x_i), m in {1,2,3}, b ~ U(-1,1),
+    evaluated as outer products of the 1D factors."""
     m = rng.integers(1, 4, (modes, 3))
     b = rng.uniform(-1.0, 1.0, modes)
-    Z, Y, X = coords(n, 3)
-    ut = np.zeros_like(X)
+    N = 2 ** n + 1
+    x = np.linspace(0.0, 1.0, N)
+    ut = np.zeros((N, N, N))
     for (mx, my, mz), bb in zip(m, b):
-        ut += bb * np.sin(mx * np.pi * X) * np.sin(my * np.pi * Y) * np.sin(mz * np.pi * Z)
+        yx = np.multiply.outer(np.sin(my * np.pi * x), bb * np.sin(mx * np.pi * x))
+        ut += np.multiply.outer(np.sin(mz * np.pi * x), yx)
     return ut
 
 
@@ -195,6 +228,29 @@ def capacitor_tanh(n=7, sign=+1):
                     extra=dict(sign=sign))
 
 
+def neumann_circle(n=6, a=0.1, radius=0.25, center=(0.5, 0.5)):
+    """Sec. 3.2, eq. 10: lap(u) + a u = f - mean(f) with zero normal derivative
+    on every face, a = 0.1, f a delta function on a circle: the curve is
+    sampled at points one mesh spacing apart (arc length h), and each point
+    deposits a tensor product of hat functions of half-width h, normalised to
+    unit integral, weighted by its arc length.  Radial 9-point stencil (the
+    2D stencil the paper reports convergence with).  No random draws.  The
+    mean is removed by the solver."""
+    N = 2 ** n + 1
+    h = 1.0 / 2 ** n
+    npts = max(8, int(round(2 * np.pi * radius / h)))
+    ds = 2 * np.pi * radius / npts
+    t = 2 * np.pi * np.arange(npts) / npts
+    f = np.zeros((N, N))
+    for px, py in zip(center[0] + radius * np.cos(t), center[1] + radius * np.sin(t)):
+        i0, j0 = int(np.floor(px / h)), int(np.floor(py / h))
+        fx, fy = px / h - i0, py / h - j0
+        for dj, wy in ((0, 1 - fy), (1, fy)):
+            for di, wx in ((0, 1 - fx), (1, fx)):
+                f[j0 + dj, i0 + di] += ds * wx * wy / (h * h)
+    return Workload("neumann_circle", 2, n, RADIAL, "NNNN", a, f)
+
+
 def random_problem(dim, n, stencil, faces, seed, hetero=True, a=0.0, dirichlet_values=True):
     """Small generic problem for parity tests: random source, smooth positive
     coefficient with random contrast, random Dirichlet values."""
@@ -213,4 +269,6 @@ CONFIGS = {
     "helmholtz3d_adjoint": helmholtz3d_adjoint,
     "poisson3d_charges": poisson3d_charges,
     "capacitor_tanh": capacitor_tanh,
+    "neumann_circle": neumann_circle,
+    "manufactured2d": manufactured2d,
 }

@@ -163,9 +163,11 @@ def test_adjoint_and_coefficient_gradient(dim, n, stencil):
     assert rel_inf(host(grad), grad_or) < 1e-12
 
 
-def test_adjoint_rejects_neumann_faces():
+def test_adjoint_rejects_pure_neumann_faces():
+    # Neumann faces next to a Dirichlet face are covered (test_gpu_neumann);
+    # with no Dirichlet face at all the adjoint is not
     from paper_1703_07206_amd import sgml
-    plan = sgml.Plan(2, 4, AXIS, "DDNN")
+    plan = sgml.Plan(2, 4, AXIS, "NNNN")
     g = torch.zeros((17, 17), dtype=torch.float64, device="cuda")
     with pytest.raises(sgml.SGMLError) as ei:
         plan.adjoint(g)

@@ -286,6 +286,41 @@ def study(max_cycles=40):
     print(json.dumps({"study": "sec31_fig3", "grid": "1025^2", "variants": out}), flush=True)
 
 
+def batch_record(wl, steps):
+    """The vector Poisson problem (three right-hand sides, one operator):
+    time to 1e-12 of the batch solve against three single solves, mixed."""
+    import torch
+    from paper_1703_07206_amd import sgml
+    k = wl.f.shape[0]
+    F = dev(wl.f)
+    plan = sgml.Plan(wl.dim, wl.n, wl.stencil, wl.faces, wl.a, None, precision=sgml.MIXED, nrhs=k)
+    single = sgml.Plan(wl.dim, wl.n, wl.stencil, wl.faces, wl.a, None, precision=sgml.MIXED)
+    U = torch.empty_like(F)
+    kw = dict(tol=TOL, max_cycles=2000, precision=sgml.MIXED, stall_window=-1)
+    plan.solve_batch(F, U=U, **kw)
+    for c in range(k):
+        single.solve(F[c], u=U[c], **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, sts = plan.solve_batch(F, U=U, **kw)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in range(k):
+            single.solve(F[c], u=U[c], **kw)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / steps
+    rec = {"workload": f"{wl.name} {wl.N}^{wl.dim} x {k} right-hand sides", "nodes": wl.nodes * k,
+           "precision": "mixed", "batch_ms": tb * 1e3, "single_solves_ms": ts * 1e3,
+           "speedup": ts / tb, "GNodes_s": wl.nodes * k / tb / 1e9,
+           "cycles": [st["cycles"] for st in sts]}
+    del plan, single, F, U
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -389,6 +424,8 @@ def main():
         cfg["poisson3d_charges_513"] = config_record(w, [("mixed", sgml.MIXED), ("fp64", sgml.FP64)], 3, 1,
                                                      adjoint_target=w.extra["u_target"])
         print("# poisson3d_charges 513^3 done", file=sys.stderr, flush=True)
+        cfg["trifoil_vortex_257_x3"] = batch_record(W.trifoil_vortex(n=8), 3)
+        print("# trifoil_vortex 257^3 x 3 done", file=sys.stderr, flush=True)
         del w
         out["configs"] = cfg
     if not args.no_cpu_baseline:

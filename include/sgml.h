@@ -216,6 +216,31 @@ sgml_status sgml_solve(sgml_plan *plan, const double *f, const double *G, double
 sgml_status sgml_solve_noalloc(sgml_plan *plan, const double *f, const double *G, double *u,
                                const sgml_opts *opts, void *stream, sgml_stats *stats);
 
+/* Batches of right-hand sides (the vector Poisson problem of Sec. 3.3 solves
+ * one equation per component with the same operator).  A batch plan holds
+ * nrhs solvers of one problem: one coefficient pyramid (built once by
+ * sgml_plan_set_coeffs) and, per right-hand side, a slice of the workspace
+ * (sgml_workspace_bytes_batch = nrhs x sgml_workspace_bytes) and, beyond the
+ * first, a stream of its own (default priority) created with the plan.
+ * sgml_solve_batch solves the first k <= nrhs right-hand sides at once:
+ *   f, u: device, k x N^d doubles (component r at offset r N^d; u may not
+ *   overlap f or G); G: device k x N^d Dirichlet values or NULL;
+ *   stats: host array of k (optional).
+ * The right-hand sides advance in lock step, one cycle each per round, on
+ * their own streams, forked from and joined to `stream` by events, so that
+ * the latency-bound coarse levels of one overlap the others' work; one host
+ * synchronisation per round serves all stop tests.  A right-hand side stops
+ * at its own tolerance.  Results equal k calls of sgml_solve.  Returns
+ * SGML_OK when all converged, else the first other status in component
+ * order.  Other entry points use the first right-hand side's solver only.
+ * nrhs <= SGML_MAX_BATCH. */
+#define SGML_MAX_BATCH 16
+size_t sgml_workspace_bytes_batch(const sgml_problem *prob, int precision, int nrhs);
+sgml_status sgml_plan_create_batch(const sgml_problem *prob, int precision, int nrhs, void *workspace,
+                                   size_t ws_bytes, sgml_plan **out);
+sgml_status sgml_solve_batch(sgml_plan *plan, int nrhs, const double *f, const double *G, double *u,
+                             const sgml_opts *opts, void *stream, sgml_stats *stats);
+
 /* Residual of a candidate solution (Sec. 2 recurrence, Sec. 3.1 norm):
  *   r = f - dL(u) at unknowns, 0 at Dirichlet nodes (r: device N^d or NULL);
  *   *rmax = max |r| (host, optional);

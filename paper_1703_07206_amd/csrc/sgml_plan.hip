@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <utility>
@@ -164,11 +165,24 @@ struct sgml_plan {
     Level *levels_host;           // pinned staging of the level table
     size_t lds_max;               // LDS bytes one workgroup may allocate
     std::vector<RunDesc> runs;        // the coarse runs of the compiled cycle, in order
+    // batches of right-hand sides: the plans of right-hand sides 1 .. nrhs-1
+    // (each with its own slice of the workspace and its own stream, forked
+    // from and joined to the caller's stream by events); their coefficient
+    // pyramid is the first plan's (sig_ws)
+    char *sig_ws = nullptr;
+    std::vector<sgml_plan *> sub;
+    std::vector<hipStream_t> sub_st;
+    std::vector<hipEvent_t> sub_ev;  // fork, join per extra right-hand side
 
     template <typename T>
     T *at(size_t off) const
     {
         return reinterpret_cast<T *>(ws + off);
+    }
+    template <typename T>
+    T *sig_at(size_t off) const
+    {
+        return reinterpret_cast<T *>((sig_ws ? sig_ws : ws) + off);
     }
     int m(int nu) const { return (1 << (n - nu)) + 1; }
     Level level(int nu) const
@@ -198,11 +212,19 @@ unsigned long long *target(sgml_plan *P, int t)
     return P->at<unsigned long long>(P->lay.scal) + (size_t)t * kRedWords;
 }
 
-// Copy reduction targets [first, first + count) to the pinned host block.
-sgml_status fetch(sgml_plan *P, int first, int count, hipStream_t st)
+// Copy reduction targets [first, first + count) to the pinned host block:
+// enqueued only (fetch_async), or enqueued and waited for (fetch).
+sgml_status fetch_async(sgml_plan *P, int first, int count, hipStream_t st)
 {
     SGML_HIP(hipMemcpyAsync(P->host + (size_t)first * kRedWords, target(P, first),
                             sizeof(unsigned long long) * kRedWords * count, hipMemcpyDeviceToHost, st));
+    return SGML_OK;
+}
+
+sgml_status fetch(sgml_plan *P, int first, int count, hipStream_t st)
+{
+    sgml_status rc = fetch_async(P, first, count, st);
+    if (rc != SGML_OK) return rc;
     SGML_HIP(hipStreamSynchronize(st));
     return SGML_OK;
 }
@@ -295,7 +317,7 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
     E[0][0] = P->at<T>(P->lay.e0);
     E[0][1] = E[0][0] + P->M;
     g[0] = src0;
-    sig[0] = P->var.sigma ? (mixed ? (const T *)P->at<T>(P->lay.sig0t) : (const T *)P->sigma) : nullptr;
+    sig[0] = P->var.sigma ? (mixed ? (const T *)P->sig_at<T>(P->lay.sig0t) : (const T *)P->sigma) : nullptr;
     ops.clear();
     updates_per_cycle = 0;
     auto push = [&](int kind, int level, int first, int target, const void *in0, const void *in1,
@@ -326,8 +348,8 @@ const T *compile_cycle(sgml_plan *P, const T *src0, const std::vector<int> &lev,
         E[nu][1] = P->at<T>(P->lay.e[nu][1]);
         T *gn = P->at<T>(P->lay.g[nu]);
         g[nu] = gn;
-        sig[nu] = P->var.sigma ? (mixed ? (const T *)P->at<T>(P->lay.sigt[nu])
-                                        : (const T *)P->at<T>(P->lay.sig64[nu]))
+        sig[nu] = P->var.sigma ? (mixed ? (const T *)P->sig_at<T>(P->lay.sigt[nu])
+                                        : (const T *)P->sig_at<T>(P->lay.sig64[nu]))
                                : nullptr;
         // restriction(nu) of the cycle source (Algorithm 1), kept for the cycle;
         // the first step may come with the source (restrict1_outside)
@@ -741,172 +763,230 @@ int coarse_level_of(const sgml_plan *P, int coarse_nodes)
     return nu;
 }
 
+// One solve of the recurrence (Sec. 2) on one plan, split into phases so that
+// several solves (right-hand sides on their own plans and streams) can run in
+// lock step: begin() up to the normaliser (synchronises its stream once) and
+// the compiled cycle; enqueue_cycle() one cycle and the copy of its residual
+// norm to the host, without waiting; finish_cycle() the stop test, after the
+// caller has synchronised the stream; end() the per-visit pseudo-residuals,
+// the W scaling of a transposed solve and the timing (synchronises).
 // wscale: the source is W^-1 f and the result is W times the solution (the
 // transposed solve, dL^T = W dL W^-1 under the node images of Neumann faces).
+template <typename T>
+struct Solve {
+    static constexpr bool mixed = sizeof(T) == 4;
+    sgml_plan *P;
+    const double *f, *G;
+    double *u;
+    const sgml_opts *o;
+    hipStream_t st;
+    bool wscale;
+    sgml_stats local;
+    sgml_stats &S;
+    Level L0;
+    std::vector<int> lev, cnt;
+    std::vector<HostOp> ops;
+    std::vector<Timed> timed;
+    long long updates_per_cycle = 0;
+    bool pure = false, z_march = false, row_march = false, done = false;
+    int i = 0, k_cur = 0, k_next = 0, chunk = 0, zreq = 0;
+    double norm0 = 0.0, last = 0.0;
+    double *s = nullptr, *s_next = nullptr, *part = nullptr, *means = nullptr;
+    T *shat = nullptr, *g1 = nullptr;
+    const T *src0 = nullptr, *e = nullptr;
+    sgml_status status = SGML_E_MAXCYCLES;
+
+    Solve(sgml_plan *P_, const double *f_, const double *G_, double *u_, const sgml_opts *o_, hipStream_t st_,
+          sgml_stats *stats, bool wscale_)
+        : P(P_), f(f_), G(G_), u(u_), o(o_), st(st_), wscale(wscale_), S(stats ? *stats : local)
+    {
+    }
+
+    sgml_status begin()
+    {
+        L0 = P->level(0);
+        s = P->at<double>(P->lay.s);
+        shat = mixed ? P->at<T>(P->lay.shat) : nullptr;
+        src0 = mixed ? shat : (const T *)s;
+        build_schedule(P->n, o->n_r, o->schedule, lev, cnt);
+        if ((int)lev.size() > SGML_MAX_VISITS) return SGML_E_ARG;
+        std::memset(&S, 0, sizeof(S));
+        S.visits = (int)lev.size();
+        if (o->profile) {
+            sgml_status rc = prof_pool(P);
+            if (rc != SGML_OK) return rc;
+        }
+        P->prof_untimed = 0;
+        SGML_HIP(hipEventRecord(P->ev0, st));
+        clear_targets(P, 1, 1, st);
+        launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), wscale, st);
+        // pure Neumann (Sec. 2, last paragraph; eq. (10)): the source minus its
+        // trapezoid mean; norm0 is that of the projected source
+        pure = P->dir == 0;
+        part = P->at<double>(P->lay.part);
+        means = P->at<double>(P->lay.means);
+        if (pure) {
+            launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
+            clear_targets(P, 1, 1, st);
+            launch_project<double>(P->dim, L0, s, u, means, nullptr, (double *)nullptr, 0.0, target(P, 1), st);
+        }
+        SGML_HIP(hipGetLastError());
+        sgml_status rc = fetch(P, 1, 1, st);
+        if (rc != SGML_OK) return rc;
+        norm0 = host_max(P, 1);
+        S.norm0 = norm0;
+        if (!(norm0 > 0.0)) {
+            // u_init = G on Dirichlet nodes, 0 elsewhere, already solves the problem
+            launch_set_dirichlet(L0, P->dim, G, u, st);
+            status = std::isfinite(norm0) ? SGML_OK : SGML_E_ARG;
+            done = true;
+            return SGML_OK;
+        }
+        // the fused cycle ends also write the next cycle's source, which a pure
+        // Neumann solve re-projects: it takes the generic cycle end
+        z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N) && !pure;
+        row_march = P->dim == 2 && o->fuse >= 0 && P->N >= 64 && !pure;
+        // the 2D row-marching cycle end of the mixed cycle also restricts the
+        // new source to level 1; it then writes the residual to the other buffer
+        g1 = mixed && row_march && P->n >= 2 ? P->at<T>(P->lay.g[1]) : nullptr;
+        s_next = g1 ? P->at<double>(P->lay.s2) : s;
+        e = compile_cycle<T>(P, src0, lev, cnt, o->record_pres != 0, coarse_level_of(P, o->coarse_nodes),
+                             o->fuse < 0 ? 0 : (o->fuse == 0 ? kDefaultFuseMin : std::max(o->fuse, 64)),
+                             g1 != nullptr, ops, updates_per_cycle);
+        rc = upload_ops<T>(P, ops, e, st);
+        if (rc != SGML_OK) return rc;
+        chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
+        zreq = o->z_chunk > 0 ? o->z_chunk : 0;                     // 0: per level
+        k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
+        if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
+        if (g1) launch_restrict<T, T>(P->dim, P->m(1), src0, g1, st);  // cycle 0's level-1 source
+        last = norm0;
+        i = 0;
+        done = o->max_cycles < 1;
+        return SGML_OK;
+    }
+
+    sgml_status enqueue_cycle()
+    {
+        const double *Gc = i == 0 ? G : nullptr;
+        clear_targets(P, 0, 1, st);
+        if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
+        timed.clear();
+        P->pev_used = 0;
+        sgml_status rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, zreq, timed, st);
+        if (rc != SGML_OK) return rc;
+        S.node_updates += updates_per_cycle;
+        // next cycle's scaling from the last known residual norm (lagged)
+        k_next = mixed ? std::ilogb(last) : 0;
+        const long ev = o->profile ? prof_pair(P) : -1;
+        if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
+        // pure Neumann: the cycle's correction is collected minus its mean
+        if (pure) launch_wmean<T>(P->dim, L0, e, std::ldexp(1.0, k_cur), part, means + 1, st);
+        if (row_march || z_march) {
+            CycleEndArgs ca;
+            ca.e = e;
+            ca.escale = std::ldexp(1.0, k_cur);
+            ca.G = Gc;
+            ca.sigma = P->sigma;
+            ca.u = u;
+            ca.s = s;
+            ca.s_out = s_next;
+            ca.shat = shat;
+            ca.shat_scale = std::ldexp(1.0, -k_next);
+            ca.norm = target(P, 0);
+            ca.g1 = g1;
+            ca.L = L0;
+            ca.chunk = chunk;
+            ca.zchunk = zreq;
+            if (z_march)
+                launch_cycle_end3d<T>(P->var, ca, st);
+            else
+                launch_cycle_end2d<T>(P->var, ca, st);
+        } else {
+            launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
+                               std::ldexp(1.0, -k_next), target(P, 0), st);
+        }
+        if (ev >= 0) {
+            SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
+            timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
+        }
+        if (pure) {
+            // s - dL(e - mean e) = s - dL e + a mean e differs from s - dL e by a
+            // constant, which the projection of the residual removes
+            launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
+            clear_targets(P, 0, 1, st);
+            launch_project<T>(P->dim, L0, s, u, means, means + 1, shat, std::ldexp(1.0, -k_next), target(P, 0),
+                              st);
+        }
+        SGML_HIP(hipGetLastError());
+        return fetch_async(P, 0, 1, st);
+    }
+
+    sgml_status finish_cycle()
+    {
+        for (auto &t : timed) {
+            float ms = 0.f;
+            SGML_HIP(hipEventElapsedTime(&ms, P->pev[t.ev], P->pev[t.ev + 1]));
+            S.prof_ms[t.cls] += ms;
+            S.prof_launches[t.cls]++;
+            S.prof_sweeps[t.cls] += t.sweeps;
+        }
+        const double norm = host_max(P, 0);
+        const double rel = norm / norm0;
+        S.cycles = i + 1;
+        S.relres = rel;
+        if (i < SGML_HIST) S.history[i] = rel;
+        k_cur = k_next;
+        last = norm;
+        std::swap(s, s_next);  // the residual the next cycle end reads
+        const int win = o->stall_window == 0 ? 3 : o->stall_window;
+        if (!std::isfinite(rel) || rel > 1e3) {
+            status = SGML_E_DIVERGED;
+            done = true;
+        } else if (rel <= o->tol) {
+            status = SGML_OK;
+            done = true;
+        } else if (win > 0 && i >= win && i < SGML_HIST && rel > 0.5 * S.history[i - win]) {
+            status = SGML_E_STAGNATED;
+            done = true;
+        }
+        ++i;
+        if (i >= o->max_cycles) done = true;
+        return SGML_OK;
+    }
+
+    sgml_status end()
+    {
+        if (o->record_pres && !ops.empty()) {
+            sgml_status rc = fetch(P, kPres, (int)lev.size(), st);
+            if (rc != SGML_OK) return rc;
+            for (size_t v = 0; v < lev.size(); ++v) S.pres[v] = host_max(P, kPres + (int)v);
+        }
+        if (wscale) launch_trap_scale(L0, P->dim, u, st);
+        SGML_HIP(hipEventRecord(P->ev1, st));
+        SGML_HIP(hipEventSynchronize(P->ev1));
+        SGML_HIP(hipEventElapsedTime(&S.ms, P->ev0, P->ev1));
+        S.prof_untimed = P->prof_untimed;
+        S.status = status;
+        return status;
+    }
+};
+
 template <typename T>
 sgml_status run_solve(sgml_plan *P, const double *f, const double *G, double *u, const sgml_opts *o,
                       hipStream_t st, sgml_stats *stats, bool wscale = false)
 {
-    const bool mixed = sizeof(T) == 4;
-    const Level L0 = P->level(0);
-    double *s = P->at<double>(P->lay.s);
-    T *shat = mixed ? P->at<T>(P->lay.shat) : nullptr;
-    const T *src0 = mixed ? shat : (const T *)s;
-    std::vector<int> lev, cnt;
-    build_schedule(P->n, o->n_r, o->schedule, lev, cnt);
-    if ((int)lev.size() > SGML_MAX_VISITS) return SGML_E_ARG;
-
-    sgml_stats local;
-    sgml_stats &S = stats ? *stats : local;
-    std::memset(&S, 0, sizeof(S));
-    S.visits = (int)lev.size();
-
-    if (o->profile) {
-        sgml_status rc = prof_pool(P);
-        if (rc != SGML_OK) return rc;
-    }
-    P->prof_untimed = 0;
-    SGML_HIP(hipEventRecord(P->ev0, st));
-    clear_targets(P, 1, 1, st);
-    launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), wscale, st);
-    // pure Neumann (Sec. 2, last paragraph; eq. (10)): the source minus its
-    // trapezoid mean; norm0 is that of the projected source
-    const bool pure = P->dir == 0;
-    double *part = P->at<double>(P->lay.part), *means = P->at<double>(P->lay.means);
-    if (pure) {
-        launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
-        clear_targets(P, 1, 1, st);
-        launch_project<double>(P->dim, L0, s, u, means, nullptr, (double *)nullptr, 0.0, target(P, 1), st);
-    }
-    SGML_HIP(hipGetLastError());
-    sgml_status rc = fetch(P, 1, 1, st);
+    Solve<T> R(P, f, G, u, o, st, stats, wscale);
+    sgml_status rc = R.begin();
     if (rc != SGML_OK) return rc;
-    const double norm0 = host_max(P, 1);
-    S.norm0 = norm0;
-    sgml_status status = SGML_E_MAXCYCLES;
-    if (!(norm0 > 0.0)) {
-        // u_init = G on Dirichlet nodes, 0 elsewhere, already solves the problem
-        launch_set_dirichlet(L0, P->dim, G, u, st);
-        status = std::isfinite(norm0) ? SGML_OK : SGML_E_ARG;
-    } else {
-        std::vector<HostOp> ops;
-        long long updates_per_cycle = 0;
-        // the fused cycle ends also write the next cycle's source, which a pure
-        // Neumann solve re-projects: it takes the generic cycle end
-        const bool z_march = P->dim == 3 && o->fuse >= 0 && sweep3d_supported(P->N) && !pure;
-        const bool row_march = P->dim == 2 && o->fuse >= 0 && P->N >= 64 && !pure;
-        // the 2D row-marching cycle end of the mixed cycle also restricts the
-        // new source to level 1; it then writes the residual to the other buffer
-        T *g1 = mixed && row_march && P->n >= 2 ? P->at<T>(P->lay.g[1]) : nullptr;
-        double *s_next = g1 ? P->at<double>(P->lay.s2) : s;
-        const T *e = compile_cycle<T>(P, src0, lev, cnt, o->record_pres != 0,
-                                      coarse_level_of(P, o->coarse_nodes),
-                                      o->fuse < 0 ? 0 : (o->fuse == 0 ? kDefaultFuseMin : std::max(o->fuse, 64)),
-                                      g1 != nullptr, ops, updates_per_cycle);
-        rc = upload_ops<T>(P, ops, e, st);
+    while (!R.done) {
+        rc = R.enqueue_cycle();
         if (rc != SGML_OK) return rc;
-        const int chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
-        const int zreq = o->z_chunk > 0 ? o->z_chunk : 0;                     // 0: per level
-        int k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
-        if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
-        if (g1) launch_restrict<T, T>(P->dim, P->m(1), src0, g1, st);  // cycle 0's level-1 source
-        double last = norm0;
-        for (int i = 0; i < o->max_cycles; ++i) {
-            const double *Gc = i == 0 ? G : nullptr;
-            clear_targets(P, 0, 1, st);
-            if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
-            std::vector<Timed> timed;
-            P->pev_used = 0;
-            rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, zreq, timed, st);
-            if (rc != SGML_OK) return rc;
-            S.node_updates += updates_per_cycle;
-            // next cycle's scaling from the last known residual norm (lagged)
-            const int k_next = mixed ? std::ilogb(last) : 0;
-            const long ev = o->profile ? prof_pair(P) : -1;
-            if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
-            // pure Neumann: the cycle's correction is collected minus its mean
-            if (pure) launch_wmean<T>(P->dim, L0, e, std::ldexp(1.0, k_cur), part, means + 1, st);
-            if (row_march || z_march) {
-                CycleEndArgs ca;
-                ca.e = e;
-                ca.escale = std::ldexp(1.0, k_cur);
-                ca.G = Gc;
-                ca.sigma = P->sigma;
-                ca.u = u;
-                ca.s = s;
-                ca.s_out = s_next;
-                ca.shat = shat;
-                ca.shat_scale = std::ldexp(1.0, -k_next);
-                ca.norm = target(P, 0);
-                ca.g1 = g1;
-                ca.L = L0;
-                ca.chunk = chunk;
-                ca.zchunk = zreq;
-                if (z_march)
-                    launch_cycle_end3d<T>(P->var, ca, st);
-                else
-                    launch_cycle_end2d<T>(P->var, ca, st);
-            } else {
-                launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
-                                   std::ldexp(1.0, -k_next), target(P, 0), st);
-            }
-            if (ev >= 0) {
-                SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
-                timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
-            }
-            if (pure) {
-                // s - dL(e - mean e) = s - dL e + a mean e differs from s - dL e by a
-                // constant, which the projection of the residual removes
-                launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
-                clear_targets(P, 0, 1, st);
-                launch_project<T>(P->dim, L0, s, u, means, means + 1, shat, std::ldexp(1.0, -k_next), target(P, 0),
-                                  st);
-            }
-            SGML_HIP(hipGetLastError());
-            rc = fetch(P, 0, 1, st);
-            if (rc != SGML_OK) return rc;
-            for (auto &t : timed) {
-                float ms = 0.f;
-                SGML_HIP(hipEventElapsedTime(&ms, P->pev[t.ev], P->pev[t.ev + 1]));
-                S.prof_ms[t.cls] += ms;
-                S.prof_launches[t.cls]++;
-                S.prof_sweeps[t.cls] += t.sweeps;
-            }
-            const double norm = host_max(P, 0);
-            const double rel = norm / norm0;
-            S.cycles = i + 1;
-            S.relres = rel;
-            if (i < SGML_HIST) S.history[i] = rel;
-            k_cur = k_next;
-            last = norm;
-            std::swap(s, s_next);  // the residual the next cycle end reads
-            if (!std::isfinite(rel) || rel > 1e3) {
-                status = SGML_E_DIVERGED;
-                break;
-            }
-            if (rel <= o->tol) {
-                status = SGML_OK;
-                break;
-            }
-            const int win = o->stall_window == 0 ? 3 : o->stall_window;
-            if (win > 0 && i >= win && i < SGML_HIST && rel > 0.5 * S.history[i - win]) {
-                status = SGML_E_STAGNATED;
-                break;
-            }
-        }
-        if (o->record_pres) {
-            rc = fetch(P, kPres, (int)lev.size(), st);
-            if (rc != SGML_OK) return rc;
-            for (size_t v = 0; v < lev.size(); ++v) S.pres[v] = host_max(P, kPres + (int)v);
-        }
+        SGML_HIP(hipStreamSynchronize(st));
+        rc = R.finish_cycle();
+        if (rc != SGML_OK) return rc;
     }
-    if (wscale) launch_trap_scale(L0, P->dim, u, st);
-    SGML_HIP(hipEventRecord(P->ev1, st));
-    SGML_HIP(hipEventSynchronize(P->ev1));
-    SGML_HIP(hipEventElapsedTime(&S.ms, P->ev0, P->ev1));
-    S.prof_untimed = P->prof_untimed;
-    S.status = status;
-    return status;
+    return R.end();
 }
 
 bool all_dirichlet(const sgml_plan *P)
@@ -1053,6 +1133,10 @@ sgml_status sgml_plan_set_coeffs(sgml_plan *P, const double *sigma, void *stream
     SGML_HIP(hipSetDevice(P->device));
     P->sigma = sigma;
     P->var.sigma = sigma ? 1 : 0;
+    for (sgml_plan *Q : P->sub) {  // a batch shares the pyramid built here
+        Q->sigma = sigma;
+        Q->var.sigma = P->var.sigma;
+    }
     if (!sigma || !P->ws) return SGML_OK;  // a plan without workspace builds it per solve
     return build_coeff_pyramid(P, st);
 }
@@ -1101,6 +1185,120 @@ sgml_status sgml_solve_noalloc(sgml_plan *P, const double *f, const double *G, d
                                         : run_solve<double>(P, f, G, u, o, st, stats);
     P->ws = own;
     if (stats) stats->status = rc;
+    return rc;
+}
+
+size_t sgml_workspace_bytes_batch(const sgml_problem *prob, int precision, int nrhs)
+{
+    if (nrhs < 1 || nrhs > SGML_MAX_BATCH) return 0;
+    return sgml_workspace_bytes(prob, precision) * (size_t)nrhs;
+}
+
+sgml_status sgml_plan_create_batch(const sgml_problem *prob, int precision, int nrhs, void *workspace,
+                                   size_t ws_bytes, sgml_plan **out)
+{
+    if (!out) return SGML_E_ARG;
+    *out = nullptr;
+    if (nrhs < 1 || nrhs > SGML_MAX_BATCH) return SGML_E_ARG;
+    const size_t one = sgml_workspace_bytes(prob, precision);
+    if (one == 0) return valid_problem(prob) && (precision == SGML_FP64 || precision == SGML_MIXED) ? SGML_E_SHAPE
+                                                                                                    : SGML_E_ARG;
+    if (!workspace || ws_bytes < one * (size_t)nrhs) return SGML_E_WORKSPACE;
+    sgml_plan *P = nullptr;
+    sgml_status rc = sgml_plan_create(prob, precision, workspace, one, &P);
+    if (rc != SGML_OK) return rc;
+    for (int r = 1; r < nrhs; ++r) {
+        sgml_plan *Q = nullptr;
+        rc = sgml_plan_create(prob, precision, static_cast<char *>(workspace) + one * (size_t)r, one, &Q);
+        hipStream_t q = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (rc == SGML_OK) {
+            Q->sig_ws = P->ws;
+            P->sub.push_back(Q);
+            // default priority; ordered against the caller's stream by events only
+            if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) rc = SGML_E_HIP;
+            else P->sub_st.push_back(q);
+        }
+        if (rc == SGML_OK) {
+            if (hipEventCreateWithFlags(&e0, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess)
+                rc = SGML_E_HIP;
+            if (e0) P->sub_ev.push_back(e0);
+            if (e1) P->sub_ev.push_back(e1);
+        }
+        if (rc != SGML_OK) {
+            sgml_plan_destroy(P);
+            return rc;
+        }
+    }
+    *out = P;
+    return SGML_OK;
+}
+
+sgml_status sgml_solve_batch(sgml_plan *P, int nrhs, const double *f, const double *G, double *u,
+                             const sgml_opts *o, void *stream, sgml_stats *stats)
+{
+    if (!P || !f || !u || !o) return SGML_E_ARG;
+    if (nrhs < 1 || nrhs > 1 + (int)P->sub.size()) return SGML_E_ARG;
+    if (o->max_cycles < 1 || !(o->tol >= 0.0)) return SGML_E_ARG;
+    if (o->precision != SGML_FP64 && o->precision != SGML_MIXED) return SGML_E_ARG;
+    if (o->precision == SGML_MIXED && P->precision != SGML_MIXED) return SGML_E_WORKSPACE;
+    if (o->schedule != SGML_SCHEDULE_ONCE && o->schedule != SGML_SCHEDULE_EACH) return SGML_E_ARG;
+    const size_t M = P->M;
+    auto overlap = [&](const double *a, const double *b) {
+        const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b, len = sizeof(double) * M * (size_t)nrhs;
+        return pa < pb + len && pb < pa + len;
+    };
+    if (overlap(u, f) || (G && overlap(u, G))) return SGML_E_ARG;
+    if (!P->ws) return SGML_E_WORKSPACE;
+    SGML_HIP(hipSetDevice(P->device));
+    hipStream_t st = (hipStream_t)stream;
+    for (int r = 1; r < nrhs; ++r) {  // fork: every stream starts after the caller's work so far
+        SGML_HIP(hipEventRecord(P->sub_ev[2 * (r - 1)], st));
+        SGML_HIP(hipStreamWaitEvent(P->sub_st[r - 1], P->sub_ev[2 * (r - 1)], 0));
+    }
+    auto run = [&](auto tag) -> sgml_status {
+        using T = decltype(tag);
+        std::vector<std::unique_ptr<Solve<T>>> runs;
+        for (int r = 0; r < nrhs; ++r)
+            runs.emplace_back(new Solve<T>(r == 0 ? P : P->sub[r - 1], f + M * r, G ? G + M * r : nullptr,
+                                           u + M * r, o, r == 0 ? st : P->sub_st[r - 1],
+                                           stats ? stats + r : nullptr, false));
+        for (auto &R : runs) {
+            sgml_status rc = R->begin();
+            if (rc != SGML_OK) return rc;
+        }
+        // lock step: every unfinished right-hand side enqueues a cycle on its
+        // stream, then all are waited for and tested
+        for (;;) {
+            bool any = false;
+            for (auto &R : runs)
+                if (!R->done) {
+                    sgml_status rc = R->enqueue_cycle();
+                    if (rc != SGML_OK) return rc;
+                    any = true;
+                }
+            if (!any) break;
+            for (auto &R : runs)
+                if (!R->done) {
+                    SGML_HIP(hipStreamSynchronize(R->st));
+                    sgml_status rc = R->finish_cycle();
+                    if (rc != SGML_OK) return rc;
+                }
+        }
+        sgml_status worst = SGML_OK;
+        for (auto &R : runs) {
+            const sgml_status rc = R->end();
+            if (rc == SGML_E_HIP) return rc;
+            if (worst == SGML_OK) worst = rc;
+        }
+        return worst;
+    };
+    const sgml_status rc = o->precision == SGML_MIXED ? run(float()) : run(double());
+    for (int r = 1; r < nrhs; ++r) {  // join: the caller's stream continues after every right-hand side
+        SGML_HIP(hipEventRecord(P->sub_ev[2 * (r - 1) + 1], P->sub_st[r - 1]));
+        SGML_HIP(hipStreamWaitEvent(st, P->sub_ev[2 * (r - 1) + 1], 0));
+    }
     return rc;
 }
 
@@ -1203,6 +1401,9 @@ const char *sgml_status_string(sgml_status s)
 void sgml_plan_destroy(sgml_plan *P)
 {
     if (!P) return;
+    for (sgml_plan *Q : P->sub) sgml_plan_destroy(Q);
+    for (hipStream_t q : P->sub_st) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : P->sub_ev) (void)hipEventDestroy(e);
     (void)hipEventDestroy(P->ev0);
     (void)hipEventDestroy(P->ev1);
     for (hipEvent_t e : P->pev) (void)hipEventDestroy(e);

@@ -81,6 +81,10 @@ def lib():
         L.sgml_plan_set_coeffs.argtypes = [vp, vp, vp]
         L.sgml_solve.argtypes = [vp, vp, vp, vp, P(Opts), vp, P(Stats)]
         L.sgml_solve_noalloc.argtypes = [vp, vp, vp, vp, P(Opts), vp, P(Stats)]
+        L.sgml_workspace_bytes_batch.restype = ctypes.c_size_t
+        L.sgml_workspace_bytes_batch.argtypes = [P(Problem), ctypes.c_int, ctypes.c_int]
+        L.sgml_plan_create_batch.argtypes = [P(Problem), ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, P(vp)]
+        L.sgml_solve_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, P(Opts), vp, vp]
         L.sgml_residual.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_double), P(ctypes.c_double), vp]
         L.sgml_adjoint.argtypes = [vp, vp, vp, P(Opts), vp, P(Stats)]
         L.sgml_coeff_grad.argtypes = [vp, vp, vp, vp, vp]
@@ -91,7 +95,8 @@ def lib():
         L.sgml_status_string.argtypes = [ctypes.c_int]
         L.sgml_plan_destroy.argtypes = [vp]
         L.sgml_plan_destroy.restype = None
-        for name in ("sgml_plan_create", "sgml_plan_set_coeffs", "sgml_solve", "sgml_solve_noalloc", "sgml_residual",
+        for name in ("sgml_plan_create", "sgml_plan_set_coeffs", "sgml_solve", "sgml_solve_noalloc", "sgml_plan_create_batch", "sgml_solve_batch",
+                     "sgml_residual",
                      "sgml_adjoint", "sgml_coeff_grad", "sgml_neumann_source", "sgml_schedule"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -149,11 +154,13 @@ class Plan:
     ``sigma`` an optional (N,)*dim float64 CUDA tensor, ``precision`` the
     highest precision mode the plan will be asked for (MIXED covers both).
     ``workspace=False`` creates a plan without a device workspace, which only
-    ``solve_noalloc`` (and ``coeff_grad``) can use.
+    ``solve_noalloc`` (and ``coeff_grad``) can use.  ``nrhs > 1`` creates a
+    batch plan for ``solve_batch`` (one workspace slice and stream per
+    right-hand side, one coefficient pyramid).
     """
 
     def __init__(self, dim, n, stencil=AXIS, faces="DDDDDD", a=0.0, sigma=None, precision=FP64,
-                 theta=0.0, device=None, workspace=True):
+                 theta=0.0, device=None, workspace=True, nrhs=1):
         L = lib()
         self.dim, self.n = dim, n
         self.N = 2 ** n + 1
@@ -162,16 +169,24 @@ class Plan:
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._prob = make_problem(dim, n, stencil, faces, a, theta)
-        nbytes = L.sgml_workspace_bytes(ctypes.byref(self._prob), precision)
+        self.nrhs = int(nrhs)
+        if self.nrhs > 1:
+            nbytes = L.sgml_workspace_bytes_batch(ctypes.byref(self._prob), precision, self.nrhs)
+        else:
+            nbytes = L.sgml_workspace_bytes(ctypes.byref(self._prob), precision)
         if nbytes == 0:
             raise SGMLError(E_ARG, "sgml_workspace_bytes")
         self.workspace_bytes = nbytes
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device) if workspace else None
             h = ctypes.c_void_p()
-            rc = L.sgml_plan_create(ctypes.byref(self._prob), precision,
-                                    self.workspace.data_ptr() if workspace else None,
-                                    nbytes if workspace else 0, ctypes.byref(h))
+            if self.nrhs > 1:
+                rc = L.sgml_plan_create_batch(ctypes.byref(self._prob), precision, self.nrhs,
+                                              self.workspace.data_ptr(), nbytes, ctypes.byref(h))
+            else:
+                rc = L.sgml_plan_create(ctypes.byref(self._prob), precision,
+                                        self.workspace.data_ptr() if workspace else None,
+                                        nbytes if workspace else 0, ctypes.byref(h))
         if rc != OK:
             raise SGMLError(rc, "sgml_plan_create")
         self._h = h
@@ -215,6 +230,23 @@ class Plan:
         if rc in (E_ARG, E_SHAPE, E_WORKSPACE, E_HIP, E_UNSUPPORTED) or (rc != OK and raise_on_failure):
             raise SGMLError(rc, "sgml_solve")
         return u, st.as_dict()
+
+    def solve_batch(self, F, G=None, U=None, raise_on_failure=True, stream=None, **kw):
+        """Solve dL(u_r) = f_r for the right-hand sides F[0..k-1] (shape
+        (k,) + grid shape) at once; G: (k,) + grid shape or None.  Returns
+        (U, list of k stats dicts)."""
+        k = F.shape[0]
+        if tuple(F.shape[1:]) != self.shape or (G is not None and tuple(G.shape) != tuple(F.shape)):
+            raise ValueError("F (and G) must have shape (k,) + the grid shape")
+        if U is None:
+            U = torch.empty_like(F)
+        o = self.opts(**kw)
+        st = (Stats * k)()
+        rc = lib().sgml_solve_batch(self._h, k, _ptr(F), _ptr(G), _ptr(U), ctypes.byref(o), _stream(stream),
+                                    ctypes.addressof(st))
+        if rc in (E_ARG, E_SHAPE, E_WORKSPACE, E_HIP, E_UNSUPPORTED) or (rc != OK and raise_on_failure):
+            raise SGMLError(rc, "sgml_solve_batch")
+        return U, [st[r].as_dict() for r in range(k)]
 
     def solve_noalloc(self, f, G=None, u=None, raise_on_failure=True, stream=None, **kw):
         """``solve`` through sgml_solve_noalloc: the library's static per-device

@@ -24,6 +24,8 @@ Helmholtz-Poisson examples):
 ``neumann_circle``   65^2 / 129^2, the grid-deformation potential of Sec. 3.2:
                      a = 0.1, zero normal derivative on every face, a delta source
                      on a circle built from tensor hats
+``trifoil_vortex``   257^3, the vector Poisson problem of Sec. 3.3: three
+                     right-hand sides (a vortex line on the trifoil knot, eq. 13)
 ``capacitor_tanh``   129^3, the heterogeneous Laplace problem of Sec. 3.4:
                      sigma = 0.55 +/- 0.45 tanh((r - 0.2)/0.1) (eq. 16), u = +1 on
                      the top and -1 on the bottom face, Neumann lateral faces
@@ -212,6 +214,43 @@ def poisson3d_charges(n=9, seed=5, ncharges=256, noise=1e-3, cutoff=8.0):
                     extra=dict(u_target=ut))
 
 
+def trifoil_vortex(n=8, r=0.2):
+    """Sec. 3.3, eq. 12-13: the vector Poisson problem lap(psi) = -omega for a
+    singular vortex line on the trifoil knot x(t) = r (sin t + 2 sin 2t,
+    cos t - 2 cos 2t, -2 sin 3t), r = 0.2, in the unit box: three right-hand
+    sides (f[c] = -omega_c, c = x, y, z) with one operator, psi = 0 on every
+    face, radial 27-point stencil.  The curve is centred on the box centre by
+    its bounding box and sampled at arc-length steps of about h; each sample
+    deposits its tangent increment dx(t) as a tensor product of hat functions
+    of half-width h (unit integral); samples whose cell leaves the box are
+    dropped.  No random draws."""
+    N = 2 ** n + 1
+    h = 1.0 / 2 ** n
+    fine = np.linspace(0.0, 2 * np.pi, 20001)
+    curve = lambda t: np.stack([r * (np.sin(t) + 2 * np.sin(2 * t)), r * (np.cos(t) - 2 * np.cos(2 * t)),  # noqa
+                                -2 * r * np.sin(3 * t)], axis=-1)
+    pts = curve(fine)
+    length = np.sum(np.linalg.norm(np.diff(pts, axis=0), axis=1))
+    centre = 0.5 - 0.5 * (pts.min(axis=0) + pts.max(axis=0))
+    npts = int(np.ceil(length / h))
+    t = 2 * np.pi * np.arange(npts) / npts
+    dt = 2 * np.pi / npts
+    x = curve(t) + 0.5 + centre - 0.5
+    dx = np.stack([r * (np.cos(t) + 4 * np.cos(2 * t)), r * (-np.sin(t) + 4 * np.sin(2 * t)),
+                   -6 * r * np.cos(3 * t)], axis=-1) * dt
+    omega = np.zeros((3, N, N, N))
+    for (px, py, pz), d in zip(x, dx):
+        i0, j0, k0 = int(np.floor(px / h)), int(np.floor(py / h)), int(np.floor(pz / h))
+        if min(i0, j0, k0) < 0 or max(i0, j0, k0) > N - 2:
+            continue
+        fx, fy, fz = px / h - i0, py / h - j0, pz / h - k0
+        for dk, wz in ((0, 1 - fz), (1, fz)):
+            for dj, wy in ((0, 1 - fy), (1, fy)):
+                for di, wx in ((0, 1 - fx), (1, fx)):
+                    omega[:, k0 + dk, j0 + dj, i0 + di] += d * (wx * wy * wz / h ** 3)
+    return Workload("trifoil_vortex", 3, n, RADIAL, "DDDDDD", 0.0, -omega, extra=dict(components=3))
+
+
 def capacitor_tanh(n=7, sign=+1):
     """Sec. 3.4: div(sigma grad u) = 0 (eq. 15) with the spherical
     coefficient of eq. 16 centred in the cube, u = -1 / +1 on the bottom /
@@ -271,4 +310,5 @@ CONFIGS = {
     "capacitor_tanh": capacitor_tanh,
     "neumann_circle": neumann_circle,
     "manufactured2d": manufactured2d,
+    "trifoil_vortex": trifoil_vortex,
 }

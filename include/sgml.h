@@ -125,6 +125,13 @@ typedef struct {
                          1024 workgroups, at most 16 / 32 planes), otherwise clamped
                          to the level (the paired relaxation balances its chunks,
                          the interpolation rounds up to an even count) */
+    int graphs;       /* >= 0 (default): the cycles after the first, which repeat
+                         the same launches, are captured once as a HIP graph
+                         (two for the two buffers of a double-buffered residual)
+                         and replayed, the graph kept by the plan for later
+                         solves with the same options, output and coefficient;
+                         < 0: every launch issued one by one.  Profiled solves
+                         never use graphs. */
 } sgml_opts;
 
 #define SGML_HIST 512

@@ -170,6 +170,16 @@ struct sgml_plan {
     // from and joined to the caller's stream by events); their coefficient
     // pyramid is the first plan's (sig_ws)
     char *sig_ws = nullptr;
+    // cycles replayed as graphs: the executable graph of a cycle (two, for the
+    // two parities of a double-buffered residual), valid for the key it was
+    // captured with; captured on a private stream
+    struct CycleGraph {
+        bool valid = false;
+        std::vector<long long> key;
+        hipGraphExec_t exec = nullptr;
+    } graph[2];
+    hipStream_t cap_st = nullptr;
+    bool graphs_broken = false;  // a capture failed once: eager from then on
     std::vector<sgml_plan *> sub;
     std::vector<hipStream_t> sub_st;
     std::vector<hipEvent_t> sub_ev;  // fork, join per extra right-hand side
@@ -788,9 +798,9 @@ struct Solve {
     std::vector<HostOp> ops;
     std::vector<Timed> timed;
     long long updates_per_cycle = 0;
-    bool pure = false, z_march = false, row_march = false, done = false;
-    int i = 0, k_cur = 0, k_next = 0, chunk = 0, zreq = 0;
-    double norm0 = 0.0, last = 0.0;
+    bool pure = false, z_march = false, row_march = false, done = false, use_graphs = false;
+    int i = 0, k0 = 0, chunk = 0, zreq = 0;
+    double norm0 = 0.0;
     double *s = nullptr, *s_next = nullptr, *part = nullptr, *means = nullptr;
     T *shat = nullptr, *g1 = nullptr;
     const T *src0 = nullptr, *e = nullptr;
@@ -857,69 +867,130 @@ struct Solve {
         if (rc != SGML_OK) return rc;
         chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
         zreq = o->z_chunk > 0 ? o->z_chunk : 0;                     // 0: per level
-        k_cur = 0;  // the cycle runs on 2^-k_cur s (exact scaling, MIXED only)
-        if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, 1.0, st);
+        // MIXED: the cycle runs on 2^-k0 s, an exact scaling that keeps the FP32
+        // values of the cycle (down to the tolerance times the source) inside
+        // the normal range; within [2^-40, 2^40] no scaling is needed
+        const int kn = mixed ? std::ilogb(norm0) : 0;
+        k0 = (kn < -40 || kn > 40) ? kn : 0;
+        if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, std::ldexp(1.0, -k0), st);
         if (g1) launch_restrict<T, T>(P->dim, P->m(1), src0, g1, st);  // cycle 0's level-1 source
-        last = norm0;
         i = 0;
         done = o->max_cycles < 1;
+        // cycles after the first (which carries the Dirichlet values) repeat the
+        // same launches: replayed as graphs unless profiling (events) or asked not to
+        use_graphs = o->graphs >= 0 && !o->profile && !P->graphs_broken;
         return SGML_OK;
     }
 
-    sgml_status enqueue_cycle()
+    // Everything a cycle enqueues, on stream q.
+    sgml_status enqueue_body(hipStream_t q)
     {
         const double *Gc = i == 0 ? G : nullptr;
-        clear_targets(P, 0, 1, st);
-        if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), st);
+        const double escale = std::ldexp(1.0, k0), sscale = std::ldexp(1.0, -k0);
+        clear_targets(P, 0, 1, q);
+        if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), q);
         timed.clear();
         P->pev_used = 0;
-        sgml_status rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, zreq, timed, st);
+        sgml_status rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, zreq, timed, q);
         if (rc != SGML_OK) return rc;
-        S.node_updates += updates_per_cycle;
-        // next cycle's scaling from the last known residual norm (lagged)
-        k_next = mixed ? std::ilogb(last) : 0;
         const long ev = o->profile ? prof_pair(P) : -1;
-        if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
+        if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], q));
         // pure Neumann: the cycle's correction is collected minus its mean
-        if (pure) launch_wmean<T>(P->dim, L0, e, std::ldexp(1.0, k_cur), part, means + 1, st);
+        if (pure) launch_wmean<T>(P->dim, L0, e, escale, part, means + 1, q);
         if (row_march || z_march) {
             CycleEndArgs ca;
             ca.e = e;
-            ca.escale = std::ldexp(1.0, k_cur);
+            ca.escale = escale;
             ca.G = Gc;
             ca.sigma = P->sigma;
             ca.u = u;
             ca.s = s;
             ca.s_out = s_next;
             ca.shat = shat;
-            ca.shat_scale = std::ldexp(1.0, -k_next);
+            ca.shat_scale = sscale;
             ca.norm = target(P, 0);
             ca.g1 = g1;
             ca.L = L0;
             ca.chunk = chunk;
             ca.zchunk = zreq;
             if (z_march)
-                launch_cycle_end3d<T>(P->var, ca, st);
+                launch_cycle_end3d<T>(P->var, ca, q);
             else
-                launch_cycle_end2d<T>(P->var, ca, st);
+                launch_cycle_end2d<T>(P->var, ca, q);
         } else {
-            launch_boundary<T>(P->var, L0, e, std::ldexp(1.0, k_cur), Gc, P->sigma, u, s, shat,
-                               std::ldexp(1.0, -k_next), target(P, 0), st);
+            launch_boundary<T>(P->var, L0, e, escale, Gc, P->sigma, u, s, shat, sscale, target(P, 0), q);
         }
         if (ev >= 0) {
-            SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
+            SGML_HIP(hipEventRecord(P->pev[ev + 1], q));
             timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
         }
         if (pure) {
             // s - dL(e - mean e) = s - dL e + a mean e differs from s - dL e by a
             // constant, which the projection of the residual removes
-            launch_wmean<double>(P->dim, L0, s, 1.0, part, means, st);
-            clear_targets(P, 0, 1, st);
-            launch_project<T>(P->dim, L0, s, u, means, means + 1, shat, std::ldexp(1.0, -k_next), target(P, 0),
-                              st);
+            launch_wmean<double>(P->dim, L0, s, 1.0, part, means, q);
+            clear_targets(P, 0, 1, q);
+            launch_project<T>(P->dim, L0, s, u, means, means + 1, shat, sscale, target(P, 0), q);
         }
         SGML_HIP(hipGetLastError());
-        return fetch_async(P, 0, 1, st);
+        return fetch_async(P, 0, 1, q);
+    }
+
+    // What a captured cycle depends on beyond the plan: the options that shape
+    // the compiled cycle, the buffers it touches and the scaling.
+    std::vector<long long> graph_key() const
+    {
+        return {(long long)sizeof(T),       o->n_r,      o->schedule,         o->record_pres,
+                o->coarse_nodes,            o->fuse,     chunk,               zreq,
+                (long long)(uintptr_t)u,    (long long)(uintptr_t)P->sigma, P->var.sigma,
+                (long long)(uintptr_t)P->ws, (long long)(uintptr_t)s, k0, pure};
+    }
+
+    // The cycle as a graph (captured on the plan's private stream the first
+    // time this key and residual buffer come up), or null to run it eagerly.
+    hipGraphExec_t cycle_graph()
+    {
+        const int slot = s == P->at<double>(P->lay.s) ? 0 : 1;
+        sgml_plan::CycleGraph &cg = P->graph[slot];
+        const std::vector<long long> key = graph_key();
+        if (cg.valid && cg.key == key) return cg.exec;
+        if (cg.exec) (void)hipGraphExecDestroy(cg.exec);
+        cg.exec = nullptr;
+        cg.valid = false;
+        if (!P->cap_st && hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking) != hipSuccess) {
+            P->cap_st = nullptr;
+            P->graphs_broken = true;
+            return nullptr;
+        }
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(P->cap_st, hipStreamCaptureModeRelaxed) == hipSuccess;
+        if (ok) {
+            ok = enqueue_body(P->cap_st) == SGML_OK;
+            ok = (hipStreamEndCapture(P->cap_st, &g) == hipSuccess) && ok && g;
+        }
+        if (ok) ok = hipGraphInstantiate(&cg.exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            (void)hipGetLastError();
+            cg.exec = nullptr;
+            P->graphs_broken = true;
+            return nullptr;
+        }
+        cg.valid = true;
+        cg.key = key;
+        return cg.exec;
+    }
+
+    sgml_status enqueue_cycle()
+    {
+        S.node_updates += updates_per_cycle;
+        if (use_graphs && i >= 1) {
+            if (hipGraphExec_t ge = cycle_graph()) {
+                SGML_HIP(hipGraphLaunch(ge, st));
+                return SGML_OK;
+            }
+            use_graphs = false;
+        }
+        return enqueue_body(st);
     }
 
     sgml_status finish_cycle()
@@ -936,8 +1007,6 @@ struct Solve {
         S.cycles = i + 1;
         S.relres = rel;
         if (i < SGML_HIST) S.history[i] = rel;
-        k_cur = k_next;
-        last = norm;
         std::swap(s, s_next);  // the residual the next cycle end reads
         const int win = o->stall_window == 0 ? 3 : o->stall_window;
         if (!std::isfinite(rel) || rel > 1e3) {
@@ -1179,10 +1248,12 @@ sgml_status sgml_solve_noalloc(sgml_plan *P, const double *f, const double *G, d
     // pyramid is rebuilt (every other region is initialised by the solve)
     char *own = P->ws;
     P->ws = static_cast<char *>(ptr);
+    sgml_opts oo = *o;
+    oo.graphs = -1;  // capturing and instantiating a graph allocates
     sgml_status rc = build_coeff_pyramid(P, st);
     if (rc == SGML_OK)
-        rc = o->precision == SGML_MIXED ? run_solve<float>(P, f, G, u, o, st, stats)
-                                        : run_solve<double>(P, f, G, u, o, st, stats);
+        rc = oo.precision == SGML_MIXED ? run_solve<float>(P, f, G, u, &oo, st, stats)
+                                        : run_solve<double>(P, f, G, u, &oo, st, stats);
     P->ws = own;
     if (stats) stats->status = rc;
     return rc;
@@ -1401,6 +1472,9 @@ const char *sgml_status_string(sgml_status s)
 void sgml_plan_destroy(sgml_plan *P)
 {
     if (!P) return;
+    for (auto &cg : P->graph)
+        if (cg.exec) (void)hipGraphExecDestroy(cg.exec);
+    if (P->cap_st) (void)hipStreamDestroy(P->cap_st);
     for (sgml_plan *Q : P->sub) sgml_plan_destroy(Q);
     for (hipStream_t q : P->sub_st) (void)hipStreamDestroy(q);
     for (hipEvent_t e : P->sub_ev) (void)hipEventDestroy(e);

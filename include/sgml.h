@@ -115,9 +115,11 @@ typedef struct {
                          the generic relaxation, transfer and cycle-end kernels in
                          2D and 3D); values below 64 act as 64 */
     int chunk_rows;   /* rows each wavefront marches through in the 2D row-marching
-                         passes; 0: chosen per launch (8 for short visits, 48 / 96
-                         (FP32 / FP64) for long visits of large levels, 96 for the
-                         cycle end), values below 8 act as 8 */
+                         passes; 0: chosen per launch (8 for short visits; for long
+                         visits of large levels the shortest chunk that keeps every
+                         wavefront of the launch resident at once; 96 for the cycle
+                         end), values below 8 act as 8, odd values are rounded up
+                         to even in the visits */
     int z_chunk;      /* planes each workgroup marches through in the 3D z-marching
                          passes (relaxation, paired relaxation, interpolation,
                          restriction, constant-coefficient cycle end) on levels of

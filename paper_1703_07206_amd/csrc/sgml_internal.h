@@ -13,6 +13,10 @@ namespace sgml {
 // arrays of this size).
 constexpr int kMaxDevices = 64;
 
+// Compute units of the current device (queried once per device; 0 when the
+// query fails).
+int device_cus();
+
 // Geometry and operator constants of one level of the nested grid
 // (Sec. 2: level nu holds the nodes whose indices are multiples of
 // lam = 2^nu; stored compactly as m^d values, m = 2^(n-nu) + 1).

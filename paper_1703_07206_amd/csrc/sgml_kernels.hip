@@ -997,6 +997,24 @@ void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level 
     dispatch3<CoarseRun<T>::template K>(v, ops, nops, levels, G, targets, st);
 }
 
+int device_cus()
+{
+    static std::mutex lock;
+    static int cus[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    std::lock_guard<std::mutex> guard(lock);
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 namespace {
 template <typename T>
 struct CoarseLdsRun {

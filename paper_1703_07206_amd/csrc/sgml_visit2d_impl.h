@@ -22,12 +22,26 @@
 #include "sgml_device.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace sgml {
 
 namespace {
 
 constexpr int kVisitBlock = 256;  // four independent wavefronts
+
+// f(std::integral_constant<int, 0>()) .. f(std::integral_constant<int, N - 1>()):
+// a loop whose index is a compile-time constant in the body.
+template <typename F, int... I>
+__device__ __forceinline__ void unroll_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void unroll(F &&f)
+{
+    unroll_seq(f, std::make_integer_sequence<int, N>());
+}
 
 // Element idx of a level array through a 32-bit byte offset (2D levels are
 // below 4 GiB): a scalar base plus one per-lane register, no 64-bit address
@@ -65,6 +79,21 @@ __device__ __forceinline__ double from_right(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A copy the compiler cannot fold into the source register (its value in a
+// new register).
+__device__ __forceinline__ float fresh(float v)
+{
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ double fresh(double v)
+{
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 // theta / D with D the local diagonal: FP32 uses the hardware reciprocal
 // (the relaxation is the approximate inner solver of the mixed mode), FP64
 // divides.
@@ -93,14 +122,22 @@ struct RowIn2 {
     T sta, stb, ga, gb, sga, sgb, c0, c1, s0, s1;
 };
 
-template <typename T, int PRO, int SIG>
+// Loads of input row rho (mirrored into the grid; a mirrored row keeps the
+// parity of rho).  The row's parity is a template argument (chunks start at
+// even rows, so it follows from the row's place in the march): every row of
+// one parity issues the same loads in the same order, with no branch, and
+// the compiler waits for each load by count at its use while the next batch
+// of rows stays in flight.  Odd rows also load the second coarse row and
+// the stale values at the coarse nodes above and below.  FIRST: the stale
+// values are zero and are not read.
+template <typename T, int PRO, int SIG, bool FIRST, bool ODD>
 __device__ __forceinline__ void load_row2(RowIn2<T> &R, const VisitArgs &A, int xma, int xmb, int rho, int m)
 {
     const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m;
     const unsigned row = rm * um;
     const T *__restrict__ estale = (const T *)A.estale;
     const T *__restrict__ g = (const T *)A.g;
-    if (PRO && A.first) {
+    if (PRO && FIRST) {
         R.sta = R.stb = T(0);
     } else {
         R.sta = ld(estale, row + (unsigned)xma);
@@ -114,19 +151,18 @@ __device__ __forceinline__ void load_row2(RowIn2<T> &R, const VisitArgs &A, int 
         R.sgb = ld(sig, row + (unsigned)xmb);
     }
     if (PRO) {
-        // coarse node X = xma / 2 (xma is even), rows Y = rm / 2 and Y + 1
+        // coarse node X = xma / 2 (xma is even), rows Y = rm / 2 and, odd
+        // rows, Y + 1 (<= mc - 1), with fine rows 2Y and 2Y + 2 (<= m - 1)
         const T *__restrict__ ec = (const T *)A.ecoarse;
         const unsigned mc = (um + 1) >> 1, Y = rm >> 1, X = (unsigned)xma >> 1;
         R.c0 = ld(ec, Y * mc + X);
-        R.c1 = R.s1 = T(0);
-        R.s0 = R.sta;  // even rows: the stale value at the coarse node is this row's
-        if (rm & 1) {
+        if (ODD) {
             R.c1 = ld(ec, (Y + 1) * mc + X);
-            if (!A.first) {
+            if (FIRST) {
+                R.s0 = R.s1 = T(0);
+            } else {
                 R.s0 = ld(estale, 2 * Y * um + (unsigned)xma);
                 R.s1 = ld(estale, (2 * Y + 2) * um + (unsigned)xma);
-            } else {
-                R.s0 = T(0);
             }
         }
     }
@@ -138,13 +174,13 @@ __device__ __forceinline__ void load_row2(RowIn2<T> &R, const VisitArgs &A, int 
 // value minus stale finer value) of the enclosing coarse nodes.  x is a coarse
 // column, x + 1 lies between coarse columns x / 2 and x / 2 + 1, the latter
 // held by the next lane.  All lanes must call it.
-template <typename T>
-__device__ __forceinline__ void prolonged2(const RowIn2<T> &R, int rm, T &va, T &vb)
+template <typename T, bool ODD>
+__device__ __forceinline__ void prolonged2(const RowIn2<T> &R, T &va, T &vb)
 {
-    if (!(rm & 1)) {
-        const T p = R.c0 - R.s0;
+    if (!ODD) {
+        const T p = R.c0 - R.sta;
         const T pr = from_right(p);
-        va = R.c0;
+        va = fresh(R.c0);  // a window value: not the loaded register (see the delay lines)
         vb = R.stb + T(0.5) * (p + pr);
     } else {
         const T p0 = R.c0 - R.s0, p1 = R.c1 - R.s1;
@@ -210,8 +246,33 @@ __device__ __forceinline__ void relax2(const T (&wa)[3], const T (&wb)[3], const
         resa = da ? T(0) : K.scale * suma + K.aw * ca - ga;
         resb = db ? T(0) : K.scale * sumb + K.aw * cb - gb;
     }
-    na = da ? gva : K.omt * ca + (K.beta * suma - K.gamma * ga);
-    nb = db ? gvb : K.omt * cb + (K.beta * sumb - K.gamma * gb);
+    // without recording, ga and gb arrive as gamma * g
+    const T gga = REC ? K.gamma * ga : ga, ggb = REC ? K.gamma * gb : gb;
+    na = da ? gva : K.omt * ca + (K.beta * suma - gga);
+    nb = db ? gvb : K.omt * cb + (K.beta * sumb - ggb);
+}
+
+// The relaxation of relax2 with a constant coefficient, no recording and no
+// Dirichlet row in the window: the damped-Jacobi form with the source
+// already scaled (gga = gamma * g) and per-lane constants, which a Dirichlet
+// column sets to omt = 1, beta = 0 and a zero source, so that it keeps its
+// value (zero after the first cycle) without a select per relaxation.
+template <typename T, int RAD>
+__device__ __forceinline__ void relax2_fast(const T (&wa)[3], const T (&wb)[3], T gga, T ggb, T oma, T omb, T bea,
+                                            T beb, T &na, T &nb)
+{
+    const T ca = wa[1], cb = wb[1];
+    const T la = from_left(cb), rb = from_right(ca);
+    T suma = (la + cb) + (wa[0] + wa[2]);
+    T sumb = (ca + rb) + (wb[0] + wb[2]);
+    if (RAD) {
+        const T ula = from_left(wb[0]), dla = from_left(wb[2]);
+        const T urb = from_right(wa[0]), drb = from_right(wa[2]);
+        suma += T(0.5) * ((ula + wb[0]) + (dla + wb[2]));
+        sumb += T(0.5) * ((wa[0] + urb) + (wa[2] + drb));
+    }
+    na = oma * ca + (bea * suma - gga);
+    nb = omb * cb + (beb * sumb - ggb);
 }
 
 template <typename T, int RAD, int SIG, int S, int PRO, int REC>
@@ -251,6 +312,10 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     const bool xdb = ((L.dir & 1u) && xmb == 0) || ((L.dir & 2u) && xmb == m - 1);
     const double *__restrict__ G = A.G;
     const int gpitch = L.lam * L.N;
+    // constants of the fast relaxation (Dirichlet columns keep their value)
+    const T oma = xda ? T(1) : K.omt, omb = xdb ? T(1) : K.omt;
+    const T bea = xda ? T(0) : K.beta, beb = xdb ? T(0) : K.beta;
+    const T gama = xda ? T(0) : K.gamma, gamb = xdb ? T(0) : K.gamma;
 
     T wa[S][3], wb[S][3];
     T gha[S + 1], ghb[S + 1];  // source at input row - k
@@ -268,33 +333,46 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
 
     const int rows = (y1 - y0) + 2 * S;
     unsigned ymask = 0;  // bit k: input row - k lies on a Dirichlet y face
-    auto step_row = [&](const RowIn2<T> &R, int t, auto hasg) {
+    auto step_row = [&](const RowIn2<T> &R, int t, auto hasg, auto odd, auto fast) __attribute__((always_inline)) {
         constexpr bool HASG = decltype(hasg)::value;
+        constexpr bool FAST = decltype(fast)::value;
         const int rho = y0 - S + t;
         const int rm = mir(rho, m);
         T va, vb;
         if (PRO) {
-            prolonged2<T>(R, rm, va, vb);
+            prolonged2<T, decltype(odd)::value>(R, va, vb);
         } else {
-            va = R.sta;
-            vb = R.stb;
+            va = fresh(R.sta);
+            vb = fresh(R.stb);
         }
 #pragma unroll
         for (int k = S; k > 0; --k) {
             gha[k] = gha[k - 1];
             ghb[k] = ghb[k - 1];
         }
-        gha[0] = R.ga;
-        ghb[0] = R.gb;
-        ymask = (ymask << 1) | (unsigned)(((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1));
+        // the source enters its delay line as gamma * g where the relaxation
+        // uses that product alone, else as a copy: either way the loaded
+        // register is free once its row is consumed, so the next batch's load
+        // reuses it (no copy of a load in flight at the end of a turn)
+        if (FAST) {
+            gha[0] = gama * R.ga;
+            ghb[0] = gamb * R.gb;
+        } else if (!SIG && !REC) {
+            gha[0] = K.gamma * R.ga;
+            ghb[0] = K.gamma * R.gb;
+        } else {
+            gha[0] = fresh(R.ga);
+            ghb[0] = fresh(R.gb);
+        }
+        if (!FAST) ymask = (ymask << 1) | (unsigned)(((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1));
         if (SIG) {
 #pragma unroll
             for (int k = S + 1; k > 0; --k) {
                 sha[k] = sha[k - 1];
                 shb[k] = shb[k - 1];
             }
-            sha[0] = R.sga;
-            shb[0] = R.sgb;
+            sha[0] = fresh(R.sga);
+            shb[0] = fresh(R.sgb);
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -304,6 +382,10 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
             wb[s][0] = wb[s][1];
             wb[s][1] = wb[s][2];
             wb[s][2] = vb;
+            if (FAST) {
+                relax2_fast<T, RAD>(wa[s], wb[s], gha[s + 1], ghb[s + 1], oma, omb, bea, beb, va, vb);
+                continue;
+            }
             const int r = rho - s - 1;  // row relaxation s+1 produces now
             const bool yd = (ymask >> (s + 1)) & 1u;
             const bool da = xda || yd, db = xdb || yd;
@@ -341,28 +423,75 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
     };
     constexpr int B = 3;
     RowIn2<T> qa[B], qb[B];
-    auto load_batch = [&](RowIn2<T>(&q)[B], int t0) {
-#pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (t0 + k < rows) load_row2<T, PRO, SIG>(q[k], A, xma, xmb, y0 - S + t0 + k, m);
+    // Row t of the march has the parity of S + t (chunks start at even
+    // rows); a turn is 2B = 6 rows, so position K of a turn has the parity
+    // of S + K.  Rows past the last one load the last row of the same parity
+    // again (the batch ahead of the tail), so that every batch issues the
+    // same loads.
+    auto load_batch = [&](RowIn2<T>(&q)[B], int t0, auto first, auto k0) __attribute__((always_inline)) {
+        constexpr bool FIRST = decltype(first)::value;
+        constexpr int K0 = decltype(k0)::value;
+        unroll<B>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            int t = t0 + k;
+            if (t > rows - 1) t -= 2 * ((t - rows + 2) >> 1);
+            load_row2<T, PRO, SIG, FIRST, ((S + K0 + k) & 1) != 0>(q[k], A, xma, xmb, y0 - S + t, m);
+        });
     };
-    auto march = [&](auto hasg) {
-        load_batch(qa, 0);
-        for (int t0 = 0; t0 < rows; t0 += 2 * B) {
-            load_batch(qb, t0 + B);
-#pragma unroll
-            for (int k = 0; k < B; ++k)
-                if (t0 + k < rows) step_row(qa[k], t0 + k, hasg);
-            load_batch(qa, t0 + 2 * B);
-#pragma unroll
-            for (int k = 0; k < B; ++k)
-                if (t0 + B + k < rows) step_row(qb[k], t0 + B + k, hasg);
+    using K0a = std::integral_constant<int, 0>;
+    using K0b = std::integral_constant<int, B>;
+    auto step_batch = [&](const RowIn2<T>(&q)[B], int t0, auto hasg, auto fast, auto k0, bool guard) __attribute__((always_inline)) {
+        constexpr int K0 = decltype(k0)::value;
+        unroll<B>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            if (!guard || t0 + k < rows)
+                step_row(q[k], t0 + k, hasg, std::integral_constant<bool, ((S + K0 + k) & 1) != 0>(), fast);
+        });
+    };
+    // two batches of B rows per turn, B a multiple of the window period
+    // (three rows), so that the windows rotate by renaming; the rows past
+    // the last full turn take the guarded tail
+    auto march = [&](auto hasg, auto first, auto fast) __attribute__((always_inline)) {
+        load_batch(qa, 0, first, K0a());
+        int t0 = 0;
+        // turns with rows after them (their refill of qa loads real rows)
+        for (; t0 + 2 * B < rows; t0 += 2 * B) {
+            load_batch(qb, t0 + B, first, K0b());
+            step_batch(qa, t0, hasg, fast, K0a(), false);
+            load_batch(qa, t0 + 2 * B, first, K0a());
+            step_batch(qb, t0 + B, hasg, fast, K0b(), false);
+        }
+        // the last turn: rows t0 .. rows - 1; in the short visits (8-row
+        // chunks, two turns) a full turn, without guards
+        if (S <= 2 && rows - t0 == 2 * B) {
+            load_batch(qb, t0 + B, first, K0b());
+            step_batch(qa, t0, hasg, fast, K0a(), false);
+            step_batch(qb, t0 + B, hasg, fast, K0b(), false);
+        } else {
+            if (t0 + B < rows) load_batch(qb, t0 + B, first, K0b());
+            step_batch(qa, t0, hasg, fast, K0a(), true);
+            step_batch(qb, t0 + B, hasg, fast, K0b(), true);
         }
     };
-    if (G)
-        march(std::true_type());
-    else
-        march(std::false_type());
+    using yes = std::true_type;
+    using no = std::false_type;
+    const bool first_visit = PRO && A.first;
+    // the fast relaxation: later cycles (Dirichlet values zero), constant
+    // coefficient, no recording, and no Dirichlet row among the rows the
+    // chunk reads (y0 - S .. y1 + S - 1)
+    const bool ydir_rows = ((L.dir & 4u) && y0 <= S) || ((L.dir & 8u) && y1 + S >= m);
+    if (G) {
+        if (first_visit) march(yes(), yes(), no());
+        else march(yes(), no(), no());
+    } else if (SIG || REC || ydir_rows) {
+        if (first_visit) march(no(), yes(), no());
+        else march(no(), no(), no());
+    } else {
+        if constexpr (!SIG && !REC) {
+            if (first_visit) march(no(), yes(), yes());
+            else march(no(), no(), yes());
+        }
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         if (!REC || A.pres[s] < 0) continue;
@@ -414,8 +543,6 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     const int x = sx * W - HX + lane;
     const int xm = mir(x, m);
     const bool xout = lane >= HX && lane < HX + W && x < m;
-    // lanes whose source value the restriction reads (owned columns and one on each side)
-    const bool xsrc = RES && lane >= 1 && lane < 63;
     const bool xdir = ((L.dir & 1u) && xm == 0) || ((L.dir & 2u) && xm == m - 1);
     const T *__restrict__ E = (const T *)A.e;
     const double *__restrict__ G = A.G;
@@ -434,7 +561,11 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     double w[3] = {0.0, 0.0, 0.0}, sw[3] = {1.0, 1.0, 1.0};
     T hs[3] = {T(0), T(0), T(0)};  // source at output rows r-2, r-1, r (RES)
     unsigned long long nb = 0;
-    // raw loads of input row rho (e, coefficient) and of output row rho - 1 (s, u)
+    // raw loads of input row rho (e, coefficient) and of output row rho - 1
+    // (s, u).  Every lane and row issues the same loads, from the mirrored
+    // column and a row clamped into the grid, so that the compiler waits for
+    // each by count at its use and the next batch stays in flight; values
+    // outside the lanes and rows that use them are ignored.
     struct Raw {
         T e;
         double sg, s, u;
@@ -444,19 +575,16 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
         const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m;
         R.e = ld(E, rm * um + (unsigned)xm);
         if (SIG) R.sg = ld(sig, rm * um + (unsigned)xm);
-        const int r = rho - 1;
-        R.s = 0.0;
-        R.u = 0.0;
-        if (r >= r_first && r < y1) {
-            if (xout || xsrc) R.s = ld(sres, (unsigned)r * um + (unsigned)xm);
-            if (xout && r >= y0) R.u = ld((const double *)u, (unsigned)r * um + (unsigned)x);
-        }
+        const unsigned rc = (unsigned)min(max(rho - 1, 0), m - 1);
+        R.s = ld(sres, rc * um + (unsigned)xm);
+        R.u = ld((const double *)u, rc * um + (unsigned)xm);
     };
-    auto step_row = [&](const Raw &R, int t) {
+    auto step_row = [&](const Raw &R, int t, auto hasg) {
+        constexpr bool HASG = decltype(hasg)::value;
         const int rho = y0 - 1 - RES + t, rm = mir(rho, m);
         const bool ydir_in = ((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1);
         double ev = escale * (double)R.e;
-        if (xdir || ydir_in) ev = G ? ld(G, (unsigned)rm * (unsigned)m + (unsigned)xm) : 0.0;  // Dirichlet values
+        if (xdir || ydir_in) ev = HASG ? ld(G, (unsigned)rm * (unsigned)m + (unsigned)xm) : 0.0;  // Dirichlet values
         w[0] = w[1];
         w[1] = w[2];
         w[2] = ev;
@@ -532,22 +660,36 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     };
     constexpr int B = 3;
     Raw qa[B], qb[B];
+    // rows past the last one load the last row again (see the visit)
     auto load_batch = [&](Raw(&q)[B], int t0) {
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (t0 + k < rows) load(q[k], t0 + k);
+        for (int k = 0; k < B; ++k) load(q[k], min(t0 + k, rows - 1));
     };
-    load_batch(qa, 0);
-    for (int t0 = 0; t0 < rows; t0 += 2 * B) {
-        load_batch(qb, t0 + B);
+    auto march = [&](auto hasg) {
+        load_batch(qa, 0);
+        int t0 = 0;
+        for (; t0 + 2 * B <= rows; t0 += 2 * B) {
+            load_batch(qb, t0 + B);
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (t0 + k < rows) step_row(qa[k], t0 + k);
-        load_batch(qa, t0 + 2 * B);
+            for (int k = 0; k < B; ++k) step_row(qa[k], t0 + k, hasg);
+            load_batch(qa, t0 + 2 * B);
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-            if (t0 + B + k < rows) step_row(qb[k], t0 + B + k);
-    }
+            for (int k = 0; k < B; ++k) step_row(qb[k], t0 + B + k, hasg);
+        }
+        if (t0 < rows) {
+            load_batch(qb, t0 + B);
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (t0 + k < rows) step_row(qa[k], t0 + k, hasg);
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (t0 + B + k < rows) step_row(qb[k], t0 + B + k, hasg);
+        }
+    };
+    if (G)
+        march(std::true_type());
+    else
+        march(std::false_type());
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long o = __shfl_xor(nb, off, 64);
@@ -558,15 +700,38 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
 
 // Rows per wavefront: short chunks give more wavefronts (the row chain of a
 // wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
-// Long visits on a large level take long chunks, longer in FP64, whose
-// register windows leave room for half as many wavefronts per CU (measured
-// on the 4097^2 level: 48 / 96 rows against 32: -12% / -10%); short visits
-// short ones (8 rows: 1% faster solves than 16, 24 or 32).
-int chunk_rows(int requested, int m, int strips, int sweeps, int elem_bytes)
+// Short visits take short chunks (8 rows: 1% faster solves than 16, 24 or
+// 32).  Long visits on a large level take the shortest chunk for which the
+// whole grid is resident at once (slots = resident wavefronts of the chip):
+// one round of workgroups, none waiting for a second.  On the 4097^2 level
+// that is 38 rows in FP32 (4 workgroups per CU) and 75 (76: chunks are
+// even) in FP64 (2 per CU,
+// the longer register windows): 69 / 130 us against 77 / 154 us for fixed
+// 48 / 96-row chunks, which leave part of the chip a fourth (third) block.
+int chunk_rows(int requested, int m, int strips, int sweeps, long long slots)
 {
     if (requested > 0) return requested;
-    if (sweeps >= 4 && (long long)strips * m >= (1 << 18)) return elem_bytes == 8 ? 96 : 48;
-    return 8;
+    if (sweeps < 4 || (long long)strips * m < (1 << 17)) return 8;
+    const long long per = slots / strips;  // chunks per strip that fill the slots once
+    if (per < 1) return std::min(m, 96);
+    return std::max(8, (int)((m + per - 1) / per));
+}
+
+// Wavefronts of one visit kernel the chip holds at once (occupancy from the
+// kernel's registers, times the compute units); 0 when unknown.
+template <typename T, int RAD, int SIG, int S, int PRO, int REC>
+long long resident_waves()
+{
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_visit2d<T, RAD, SIG, S, PRO, REC>, kVisitBlock, 0) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            b = 0;
+        }
+        return b;
+    }();
+    return (long long)per_cu * device_cus() * (kVisitBlock / 64);
 }
 
 template <typename T, int RAD, int SIG, int S, int PRO, int REC>
@@ -575,8 +740,11 @@ void launch_one(const VisitArgs &a0, hipStream_t st)
     VisitArgs a = a0;
     const int m = a.L.m;
     constexpr int W = 128 - 2 * ((S + PRO + 1) / 2 * 2);
-    a.chunk = chunk_rows(a0.chunk, m, 2 * ((m + W - 1) / W), S, (int)sizeof(T));
-    const long long waves = (long long)((m + W - 1) / W) * ((m + a.chunk - 1) / a.chunk);
+    const int strips = (m + W - 1) / W;
+    if (a0.chunk <= 0 && S >= 4) a.chunk = chunk_rows(0, m, strips, S, resident_waves<T, RAD, SIG, S, PRO, REC>());
+    else a.chunk = chunk_rows(a0.chunk, m, strips, S, 0);
+    a.chunk += a.chunk & 1;  // chunks start at even rows: row parity follows from the place in the march
+    const long long waves = (long long)strips * ((m + a.chunk - 1) / a.chunk);
     const unsigned blocks = (unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64));
     hipLaunchKernelGGL((k_visit2d<T, RAD, SIG, S, PRO, REC>), dim3(blocks), dim3(kVisitBlock), 0, st, a);
 }

@@ -137,8 +137,9 @@ def bytes_per_node(wl, name, tb):
     """Algorithmic HBM bytes per node and launch of a level-0 kernel class,
     tb = bytes of the cycle's precision (4 mixed, 8 FP64).
       2D fused visit (interpolation prologue + relaxations): read e (stale),
-        source, coarse e (1/4 of the nodes); write e; with injection also the
-        coarse write (1/4)
+        source, coarse e (1/4 of the nodes); write e; the visit with injection
+        (the cycle's first visit of level 0, whose stale values are zero and
+        not read) reads no stale e and also writes the coarse level (1/4)
       3D relaxation (sweep0): read e, source (and the FP32/FP64 coefficient
         when heterogeneous), write e; the paired sigma = 1 relaxation moves
         the same bytes for two relaxations
@@ -150,7 +151,7 @@ def bytes_per_node(wl, name, tb):
     if name == "visit0":
         return 3 * tb + tb / 4
     if name == "visit0_inject":
-        return 3 * tb + tb / 2
+        return 2 * tb + tb / 2
     if name == "sweep0":
         return 3 * tb + (tb if sig else 0)
     if name == "cycle_end":

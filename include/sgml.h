@@ -118,8 +118,9 @@ typedef struct {
                          passes; 0: chosen per launch (8 for short visits; for long
                          visits of large levels the shortest chunk that keeps every
                          wavefront of the launch resident at once; 96 for the cycle
-                         end), values below 8 act as 8, odd values are rounded up
-                         to even in the visits */
+                         end, fewer on levels too small to fill the device), values
+                         below 8 act as 8, odd values are rounded up to even in the
+                         visits */
     int z_chunk;      /* planes each workgroup marches through in the 3D z-marching
                          passes (relaxation, paired relaxation, interpolation,
                          restriction, constant-coefficient cycle end) on levels of

@@ -1,6 +1,6 @@
 // sgml_visit2d_f32.hip -- the 2D row-marching visit and cycle-end pass in
-// float (the kernels are in sgml_visit2d_impl.h; one precision per file so
-// that the two compile in parallel).
+// float, axis stencil (the kernels are in sgml_visit2d_impl.h; one precision
+// and stencil per file so that the four compile in parallel).
 #include "sgml_visit2d_impl.h"
 
 namespace sgml {
@@ -9,5 +9,6 @@ bool fused_visit_supported(int sweeps) { return sweeps == 1 || sweeps == 2 || sw
 
 template void launch_cycle_end2d<float>(const Variant &, const CycleEndArgs &, hipStream_t);
 template void launch_visit2d<float>(const Variant &, const VisitArgs &, hipStream_t);
+template void launch_visit2d_r<float, 0>(const VisitArgs &, bool, hipStream_t);
 
 }  // namespace sgml

@@ -784,10 +784,16 @@ void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st
     CycleEndArgs a = a0;
     const int m = a.L.m;
     const bool res = a.g1 != nullptr && a.s_out != nullptr && a.s_out != a.s;
-    a.chunk = a0.chunk > 0 ? a0.chunk : 96;  // measured on 4097^2: 96 rows ahead of 32, 64 and 128
-    if (res) a.chunk = (a.chunk + 1) & ~1;  // chunks start at even rows
     const int W = res ? 60 : 62;
-    const long long waves = (long long)((m + W - 1) / W) * ((m + a.chunk - 1) / a.chunk);
+    const long long strips = (m + W - 1) / W;
+    // 96 rows per wavefront (measured on 4097^2 against 8..128: within 4%);
+    // a level too small to give the chip's 1024 SIMDs a wavefront each at 96
+    // rows takes shorter chunks (129^2: 8 rows, 51 wavefronts instead of 6)
+    a.chunk = a0.chunk > 0 ? a0.chunk : 96;
+    if (a0.chunk <= 0 && strips * ((m + 95) / 96) < 1024)
+        a.chunk = std::max(8, (int)(((long long)m * strips + 1023) / 1024));
+    if (res) a.chunk = (a.chunk + 1) & ~1;  // chunks start at even rows
+    const long long waves = strips * ((m + a.chunk - 1) / a.chunk);
     const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
 #define SGML_CE(R, S)                                                                       \
     if (res)                                                                                \
@@ -807,17 +813,29 @@ void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st
 }
 
 
+// The visits of one stencil (RAD), with or without a coefficient field;
+// each (precision, stencil) pair is instantiated in a file of its own, so
+// that the four compile in parallel.
+template <typename T, int RAD>
+void launch_visit2d_r(const VisitArgs &a, bool sigma, hipStream_t st)
+{
+    if (sigma)
+        launch_rs<T, RAD, 1>(a, st);
+    else
+        launch_rs<T, RAD, 0>(a, st);
+}
+extern template void launch_visit2d_r<float, 0>(const VisitArgs &, bool, hipStream_t);
+extern template void launch_visit2d_r<float, 1>(const VisitArgs &, bool, hipStream_t);
+extern template void launch_visit2d_r<double, 0>(const VisitArgs &, bool, hipStream_t);
+extern template void launch_visit2d_r<double, 1>(const VisitArgs &, bool, hipStream_t);
+
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st)
 {
-    if (v.radial && v.sigma)
-        launch_rs<T, 1, 1>(a, st);
-    else if (v.radial)
-        launch_rs<T, 1, 0>(a, st);
-    else if (v.sigma)
-        launch_rs<T, 0, 1>(a, st);
+    if (v.radial)
+        launch_visit2d_r<T, 1>(a, v.sigma, st);
     else
-        launch_rs<T, 0, 0>(a, st);
+        launch_visit2d_r<T, 0>(a, v.sigma, st);
 }
 
 

@@ -86,6 +86,22 @@ struct LdsOp {
     int pad;
     const void *sig;  // sweeps: level coefficient (global memory) or null
     Level L;          // sweeps: constants of the level
+    // sweeps: the relaxation's constants in the cycle's precision, computed
+    // once on the host (index kK*): level scale, a, theta, theta / D with the
+    // sigma = 1 diagonal D, 1 - theta, theta scale / D, a - 4 scale
+    float kf[8];
+    double kd[8];
+};
+enum { kKScale = 0, kKA, kKTheta, kKStep, kKOmt, kKBeta, kKAw };
+// An operation as the LDS run keeps it in LDS: the fields its control flow
+// and arithmetic use, the constants in the cycle's precision.
+template <typename T>
+struct LdsOpHdr {
+    int kind, m, nodes, target, solo, sync, in0, in1, out, first, lam, N;
+    unsigned dir;
+    float inv_m;
+    const void *sig;
+    T k[8];
 };
 // A copy between global memory and the LDS image before (loads) or after
 // (stores) the run.
@@ -145,10 +161,11 @@ template <typename T>
 void launch_coarse(const Variant &v, const CoarseOp *ops, int nops, const Level *levels, const double *G,
                    unsigned long long *targets, hipStream_t st);
 
-// `lds_bytes` covers the level arrays and, from byte ops_off on, the nops
-// operations.  Returns false when the launch cannot get that much LDS.
+// `lds_bytes` covers the level arrays and, from byte hdr_off on, the nops
+// operation headers (LdsOpHdr<T>).  Returns false when the launch cannot get
+// that much LDS.
 template <typename T>
-bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload,
+bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int hdr_off, const LdsXfer *xfer, int nload,
                        int nstore, size_t lds_bytes, const double *G, unsigned long long *targets, hipStream_t st);
 
 template <typename T>

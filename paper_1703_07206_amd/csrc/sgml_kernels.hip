@@ -407,8 +407,9 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse(const CoarseOp *
 // The coarse run of k_coarse with its level arrays in LDS: the arrays the run
 // reads before writing are copied in, every operation works LDS to LDS (one
 // barrier each), and the arrays read after the run are copied back.  The
-// operation list is copied in too (at ops_off bytes), so that no operation
-// waits on a global load.  Thread
+// operations' headers are staged in LDS too (one per thread, all at once),
+// with the relaxation constants precomputed on the host; the next header is
+// read while the current operation runs.  Thread
 // t owns nodes t, t + threads, ... of the level an operation writes; it
 // computes all of them before storing any, so the loads of a thread issue
 // together.  Each operation reads one buffer of a level and writes the other
@@ -422,23 +423,42 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse(const CoarseOp *
 // wavefront has all the parallelism there is.
 template <typename T, int DIM, int RAD, int SIG>
 __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp *__restrict__ ops, int nops,
-                                                               int ops_off, const LdsXfer *__restrict__ xfer,
+                                                               int hdr_off, const LdsXfer *__restrict__ xfer,
                                                                int nload, int nstore,
                                                                const double *__restrict__ G,
                                                                unsigned long long *__restrict__ targets)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    using Hdr = LdsOpHdr<T>;
     T *sm = reinterpret_cast<T *>(lds_raw);
-    LdsOp *sops = reinterpret_cast<LdsOp *>(lds_raw + ops_off);
+    Hdr *hdr = reinterpret_cast<Hdr *>(lds_raw + hdr_off);
     constexpr int NT = coarse_threads(DIM);
     constexpr int KMAX = coarse_lds_nodes(DIM) / NT;
-    static_assert(sizeof(LdsOp) % 4 == 0, "LdsOp is copied as words");
     const int tid = threadIdx.x;
-    {
-        const unsigned *src = reinterpret_cast<const unsigned *>(ops);
-        unsigned *dst = reinterpret_cast<unsigned *>(sops);
-        const int words = nops * (int)(sizeof(LdsOp) / 4);
-        for (int t = tid; t < words; t += NT) dst[t] = src[t];
+    for (int q = tid; q < nops; q += NT) {
+        const LdsOp &g = ops[q];
+        Hdr h;
+        h.kind = g.kind;
+        h.m = g.m;
+        h.nodes = g.nodes;
+        h.target = g.target;
+        h.solo = g.solo;
+        h.sync = g.sync;
+        h.in0 = g.in0;
+        h.in1 = g.in1;
+        h.out = g.out;
+        h.first = g.first;
+        h.lam = g.L.lam;
+        h.N = g.L.N;
+        h.dir = g.L.dir;
+        h.inv_m = g.inv_m;
+        h.sig = g.sig;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if constexpr (sizeof(T) == 4) h.k[c] = g.kf[c];
+            else h.k[c] = g.kd[c];
+        }
+        hdr[q] = h;
     }
     for (int x = 0; x < nload; ++x) {
         const T *src = static_cast<const T *>(xfer[x].ptr);
@@ -449,8 +469,9 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
     __syncthreads();
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // first node of this wave
     const int lane = tid & 63;
+    Hdr op = hdr[0];
     for (int o = 0; o < nops; ++o) {
-        const LdsOp &op = sops[o];
+        const Hdr nxt = hdr[o + 1 < nops ? o + 1 : o];  // in flight during this operation
         // uniform over the workgroup: the fields the control flow uses go to scalars
         const int kind = __builtin_amdgcn_readfirstlane(op.kind);
         const int m = __builtin_amdgcn_readfirstlane(op.m);
@@ -496,19 +517,23 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
             case kOpSweep: {
                 const T *ein = sm + in0, *g = sm + in1;
                 const T *sig = static_cast<const T *>(op.sig);
-                const Level L = op.L;
+                Level L;  // the geometry lds_sweep_value reads; the constants are in K
+                L.scale = L.a = L.theta = 0.0;
+                L.m = m;
+                L.lam = __builtin_amdgcn_readfirstlane(op.lam);
+                L.N = __builtin_amdgcn_readfirstlane(op.N);
+                L.dir = __builtin_amdgcn_readfirstlane(op.dir);
+                const auto kc = [&](int q) -> T { return op.k[q]; };
                 SweepConst<T> K;
-                K.scale = (T)L.scale;
-                K.a = (T)L.a;
-                K.theta = (T)L.theta;
-                K.step = K.theta / const_diag<T, DIM, RAD>(K.scale, K.a);
+                K.scale = kc(kKScale);
+                K.a = kc(kKA);
+                K.theta = kc(kKTheta);
+                K.step = kc(kKStep);
                 const bool want_rb = target >= 0;
                 if (DIM == 2 && !RAD && !SIG) {
                     // 5-point, sigma = 1: e' = (1 - theta) e + beta (sum of neighbours) - gamma g,
                     // beta = theta scale / D, gamma = theta / D; images at the faces
-                    const T Dc = const_diag<T, DIM, RAD>(K.scale, K.a);
-                    const T omt = T(1) - K.theta, beta = K.theta * K.scale / Dc, gamma = K.theta / Dc;
-                    const T aw = K.a - T(4) * K.scale;
+                    const T omt = kc(kKOmt), beta = kc(kKBeta), gamma = K.step, aw = kc(kKAw);
                     const unsigned dir = L.dir;
                     each([&](int t, int i, int j, int) {
                         const int il = i > 0 ? t - 1 : t + 1, ir = i < m - 1 ? t + 1 : t - 1;
@@ -564,6 +589,7 @@ __global__ __launch_bounds__(coarse_threads(DIM)) void k_coarse_lds(const LdsOp 
             __syncthreads();
         else  // solo, within a section: wavefront 0's writes complete before its next reads
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        op = nxt;
     }
     for (int x = nload; x < nload + nstore; ++x) {
         T *dst = static_cast<T *>(xfer[x].ptr);
@@ -1020,7 +1046,7 @@ template <typename T>
 struct CoarseLdsRun {
     template <int D, int R, int S>
     struct K {
-        static bool run(const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload, int nstore,
+        static bool run(const LdsOp *ops, int nops, int hdr_off, const LdsXfer *xfer, int nload, int nstore,
                         size_t bytes, const double *G, unsigned long long *targets, hipStream_t st)
         {
             // dynamic LDS this instantiation may use, per device; raised under a
@@ -1041,7 +1067,7 @@ struct CoarseLdsRun {
                 }
             }
             hipLaunchKernelGGL((k_coarse_lds<T, D, R, S>), dim3(1), dim3(coarse_threads(D)), bytes, st, ops,
-                               nops, ops_off, xfer, nload, nstore, G, targets);
+                               nops, hdr_off, xfer, nload, nstore, G, targets);
             return true;
         }
     };
@@ -1049,10 +1075,10 @@ struct CoarseLdsRun {
 }  // namespace
 
 template <typename T>
-bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int ops_off, const LdsXfer *xfer, int nload,
+bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int hdr_off, const LdsXfer *xfer, int nload,
                        int nstore, size_t lds_bytes, const double *G, unsigned long long *targets, hipStream_t st)
 {
-    return dispatch3r<bool, CoarseLdsRun<T>::template K>(v, ops, nops, ops_off, xfer, nload, nstore, lds_bytes, G,
+    return dispatch3r<bool, CoarseLdsRun<T>::template K>(v, ops, nops, hdr_off, xfer, nload, nstore, lds_bytes, G,
                                                          targets, st);
 }
 
@@ -1260,10 +1286,10 @@ template void launch_coarse<double>(const Variant &, const CoarseOp *, int, cons
                                     unsigned long long *, hipStream_t);
 template void launch_coarse<float>(const Variant &, const CoarseOp *, int, const Level *, const double *,
                                    unsigned long long *, hipStream_t);
-template bool launch_coarse_lds<double>(const Variant &, const LdsOp *, int, int, const LdsXfer *, int, int,
-                                        size_t, const double *, unsigned long long *, hipStream_t);
-template bool launch_coarse_lds<float>(const Variant &, const LdsOp *, int, int, const LdsXfer *, int, int,
-                                       size_t, const double *, unsigned long long *, hipStream_t);
+template bool launch_coarse_lds<double>(const Variant &, const LdsOp *, int, int, const LdsXfer *, int, int, size_t,
+                                        const double *, unsigned long long *, hipStream_t);
+template bool launch_coarse_lds<float>(const Variant &, const LdsOp *, int, int, const LdsXfer *, int, int, size_t,
+                                       const double *, unsigned long long *, hipStream_t);
 template void launch_prolong<double>(int, int, const double *, const double *, double *, bool, hipStream_t);
 template void launch_prolong<float>(int, int, const float *, const float *, float *, bool, hipStream_t);
 template void launch_inject<double>(int, int, const double *, double *, hipStream_t);

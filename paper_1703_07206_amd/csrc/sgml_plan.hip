@@ -135,8 +135,8 @@ struct RunDesc {
     int op0, nops;             // range of the device CoarseOp list (k_coarse)
     int lds;                   // staged in LDS (k_coarse_lds)
     int lop0, x0, nload, nstore;
-    int ops_off;               // LDS byte offset of the staged operation list
     size_t lds_bytes;
+    int hdr_off;               // LDS byte offset of the staged operation headers
 };
 
 }  // namespace
@@ -523,6 +523,32 @@ int op_refs(const sgml_plan *P, const HostOp &h, Ref r[6])
     return k;
 }
 
+// The constants of a constant-coefficient relaxation on level L, in the
+// order of the kK* indices, in float and in double: each precision's values
+// come from that precision's arithmetic on the level's scale, a and theta
+// (the diagonal D = W scale - a, W = 2 dim + 1/2 x edge neighbours + 1/3 x
+// corner neighbours of the stencil).
+template <typename R>
+void relax_constants_as(int dim, int radial, const Level &L, R *k)
+{
+    const int n2 = radial ? (dim == 3 ? 12 : 4) : 0, n3 = (radial && dim == 3) ? 8 : 0;
+    const R scale = (R)L.scale, a = (R)L.a, theta = (R)L.theta;
+    const R W = R(2 * dim) + R(0.5) * R(n2) + R(1.0 / 3.0) * R(n3);
+    const R D = scale * W - a;
+    k[kKScale] = scale;
+    k[kKA] = a;
+    k[kKTheta] = theta;
+    k[kKStep] = theta / D;
+    k[kKOmt] = R(1) - theta;
+    k[kKBeta] = theta * scale / D;
+    k[kKAw] = a - R(4) * scale;
+}
+void relax_constants(int dim, int radial, const Level &L, float *kf, double *kd)
+{
+    relax_constants_as<float>(dim, radial, L, kf);
+    relax_constants_as<double>(dim, radial, L, kd);
+}
+
 // Stage one run [i, j) of coarse operations in LDS: every buffer it touches
 // gets an LDS slot; a buffer is loaded when the run reads it before writing
 // it, and stored when the next reference after the run (the cycle repeats,
@@ -560,8 +586,8 @@ bool stage_lds_run(sgml_plan *P, const std::vector<HostOp> &ops, const void *liv
             if (r[q].write) slots[s].written = true;
         }
     }
-    const size_t ops_off = (elems * sizeof(T) + 15) / 16 * 16;
-    const size_t bytes = ops_off + (j - i) * sizeof(LdsOp);
+    const size_t hdr_off = (elems * sizeof(T) + 15) / 16 * 16;
+    const size_t bytes = hdr_off + (j - i) * sizeof(LdsOpHdr<T>);
     const size_t budget = P->lds_max > 1024 ? P->lds_max - 1024 : 0;  // static LDS of the kernel
     if (bytes > budget || nl + (j - i) > (size_t)kMaxCoarseOps || nx + 2 * slots.size() > (size_t)kMaxXfers)
         return false;
@@ -584,7 +610,7 @@ bool stage_lds_run(sgml_plan *P, const std::vector<HostOp> &ops, const void *liv
     R.lop0 = nl;
     R.x0 = nx;
     R.lds_bytes = bytes;
-    R.ops_off = (int)ops_off;
+    R.hdr_off = (int)hdr_off;
     for (size_t k = i; k < j; ++k) {
         const CoarseOp &o = ops[k].op;
         LdsOp &lo = P->lops_host[nl++];
@@ -603,6 +629,7 @@ bool stage_lds_run(sgml_plan *P, const std::vector<HostOp> &ops, const void *liv
         lo.sync = 1;
         lo.sig = o.in2;
         lo.L = P->level(o.level);
+        relax_constants(P->dim, P->var.radial, lo.L, lo.kf, lo.kd);
     }
     for (int q = R.lop0; q + 1 < nl; ++q)  // a solo operation followed by another needs no barrier
         if (P->lops_host[q].solo && P->lops_host[q + 1].solo) P->lops_host[q].sync = 0;
@@ -683,8 +710,9 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             while (j < ops.size() && ops[j].coarse) ++j;
             if (run >= P->runs.size()) return SGML_E_ARG;
             const RunDesc &R = P->runs[run++];
-            const bool staged = R.lds && launch_coarse_lds<T>(P->var, dev_lops + R.lop0, R.nops, R.ops_off, dev_xfer + R.x0,
-                                                              R.nload, R.nstore, R.lds_bytes, G, targets, st);
+            const bool staged = R.lds && launch_coarse_lds<T>(P->var, dev_lops + R.lop0, R.nops, R.hdr_off,
+                                                              dev_xfer + R.x0, R.nload, R.nstore, R.lds_bytes, G,
+                                                              targets, st);
             if (!staged) launch_coarse<T>(P->var, dev_ops + R.op0, R.nops, dev_levels, G, targets, st);
             i = j;
             continue;

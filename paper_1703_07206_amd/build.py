@@ -17,8 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsgml.so")
 SOURCES = ["sgml_visit2d_f32.hip", "sgml_visit2d_f64.hip", "sgml_visit2d_f32r.hip", "sgml_visit2d_f64r.hip",
-           "sgml_kernels.hip", "sgml_tile2d.hip",
-           "sgml_sweep3d.hip", "sgml_plan.hip"]
+           "sgml_kernels.hip", "sgml_sweep3d.hip", "sgml_plan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [

@@ -171,12 +171,6 @@ bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int hdr_off
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
 
-// The same visit on a 2D level, tile by tile in LDS, for the levels coarser
-// than 0 that tile_visit_supported accepts.
-bool tile_visit_supported(int m);
-template <typename T>
-void launch_visit_tile(const Variant &v, const VisitArgs &a, hipStream_t st);
-
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st);
 

@@ -727,10 +727,7 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
             const int cls = a.inject ? SGML_PROF_VISIT0_INJ : SGML_PROF_VISIT0;
             const long ev = (profile && o.level == 0) ? prof_pair(P) : -1;
             if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], st));
-            if (o.level > 0 && tile_visit_supported(o.m))
-                launch_visit_tile<T>(P->var, a, st);
-            else
-                launch_visit2d<T>(P->var, a, st);
+            launch_visit2d<T>(P->var, a, st);
             if (ev >= 0) {
                 SGML_HIP(hipEventRecord(P->pev[ev + 1], st));
                 timed.push_back({cls, a.sweeps, ev});

@@ -22,7 +22,7 @@ def dev(x):
 CASES = [
     # dim, n, stencil, faces, heterogeneous sigma, a, Dirichlet values
     (2, 10, AXIS, "DDNN", False, 0.0, True),     # row-marching visits, double-buffered residual (mixed)
-    (2, 8, RADIAL, "DNND", True, -0.3, True),    # tiles, coarse kernel
+    (2, 8, RADIAL, "DNND", True, -0.3, True),    # row-marching visits with a coefficient, coarse kernel
     (3, 6, RADIAL, "DDDDDD", False, 0.0, True),  # z-marching paired relaxations, LDS cycle end
     (3, 5, AXIS, "NDNDDN", True, -0.2, True),    # single 3D relaxations
     (2, 7, RADIAL, "NNNN", False, 0.1, False),   # pure Neumann projections

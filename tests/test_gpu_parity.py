@@ -279,8 +279,8 @@ def test_fused_visits_converged(case):
                          ids=["n10-axis-DDNN-one", "n10-rad-NDDN-sig"])
 def test_per_cycle_parity_1025(case):
     # every 2D kernel of the default path at once: the row-marching visits of
-    # level 0, LDS-tiled visits of levels 1..3 (513^2..129^2), the coarse
-    # levels in LDS, and the cycle end (mixed: with the level-1 restriction)
+    # levels 0..3 (1025^2..129^2), the coarse levels in LDS, and the cycle end
+    # (mixed: with the level-1 restriction)
     dim, n, stencil, faces, hetero, a, with_G = case
     wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1500 + n)
     P = oracle_problem(wl)

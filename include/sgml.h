@@ -104,18 +104,19 @@ typedef struct {
     int coarse_nodes; /* levels of at most this many nodes run together in one
                          single-workgroup launch per run of coarse operations
                          (their arrays staged in LDS when they fit);
-                         0: default (5000), < 0: every operation launched alone */
+                         0: default (1100 in 2D, 5000 in 3D), < 0: every operation
+                         launched alone */
     int stall_window; /* SGML_E_STAGNATED when the residual has not halved over
                          this many cycles; 0: default (3), < 0: never */
     int fuse;         /* 2D levels with at least this many nodes per axis (and
                          too large for the coarse kernel) run each visit as one
-                         fused pass (LDS tiles up to 1025 nodes per axis,
-                         row-marching above); 0: default (129), < 0: never (one
+                         fused row-marching pass; 0: default (65), < 0: never (one
                          launch per interpolation, relaxation and injection, and
                          the generic relaxation, transfer and cycle-end kernels in
                          2D and 3D); values below 64 act as 64 */
     int chunk_rows;   /* rows each wavefront marches through in the 2D row-marching
-                         passes; 0: chosen per launch (8 for short visits; for long
+                         passes; 0: chosen per launch (8 for short visits, 4 on
+                         levels of at most 1025 nodes per axis; for long
                          visits of large levels the shortest chunk that keeps every
                          wavefront of the launch resident at once; 96 for the cycle
                          end, fewer on levels too small to fill the device), values

@@ -700,8 +700,10 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
 
 // Rows per wavefront: short chunks give more wavefronts (the row chain of a
 // wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
-// Short visits take short chunks (8 rows: 1% faster solves than 16, 24 or
-// 32).  Long visits on a large level take the shortest chunk for which the
+// Short visits take short chunks: 8 rows (1% faster solves than 16, 24 or
+// 32), 4 on levels of at most 1025 nodes per axis, which have few wavefronts
+// to spread their latency over (1% faster than 8 on the 4097^2 and 129^2
+// solves).  Long visits on a large level take the shortest chunk for which the
 // whole grid is resident at once (slots = resident wavefronts of the chip):
 // one round of workgroups, none waiting for a second.  On the 4097^2 level
 // that is 38 rows in FP32 (4 workgroups per CU) and 75 (76: chunks are
@@ -711,7 +713,7 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
 int chunk_rows(int requested, int m, int strips, int sweeps, long long slots)
 {
     if (requested > 0) return requested;
-    if (sweeps < 4 || (long long)strips * m < (1 << 17)) return 8;
+    if (sweeps < 4 || (long long)strips * m < (1 << 17)) return m <= 1025 ? 4 : 8;
     const long long per = slots / strips;  // chunks per strip that fill the slots once
     if (per < 1) return std::min(m, 96);
     return std::max(8, (int)((m + per - 1) / per));

@@ -145,7 +145,9 @@ def bytes_per_node(wl, name, tb):
         the same bytes for two relaxations
       cycle end: read e, u, s; write u, s (FP64); mixed: write the next source
         (FP32) and, in 2D, its restriction to level 1 (1/4 of the nodes); the
-        FP64 coefficient when heterogeneous"""
+        FP64 coefficient when heterogeneous
+      closing visit and cycle end in one pass (2D mixed): the visit's reads
+        (stale e, source, coarse e) and the cycle end's bytes without e"""
     mixed = tb == 4
     sig = wl.sigma is not None
     if name == "visit0":
@@ -154,6 +156,8 @@ def bytes_per_node(wl, name, tb):
         return 2 * tb + tb / 2
     if name == "sweep0":
         return 3 * tb + (tb if sig else 0)
+    if name == "visit0_end":
+        return 2 * tb + tb / 4 + 32 + 4 + tb / 4
     if name == "cycle_end":
         return tb + 32 + (4 if mixed else 0) + (tb / 4 if mixed and wl.dim == 2 else 0) + (8 if sig else 0)
     raise KeyError(name)

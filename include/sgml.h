@@ -140,8 +140,14 @@ typedef struct {
 
 #define SGML_HIST 512
 #define SGML_MAX_VISITS 128
-#define SGML_PROF_CLASSES 4
-enum { SGML_PROF_SWEEP0 = 0, SGML_PROF_VISIT0_INJ = 1, SGML_PROF_VISIT0 = 2, SGML_PROF_CYCLE_END = 3 };
+#define SGML_PROF_CLASSES 5
+enum {
+    SGML_PROF_SWEEP0 = 0,
+    SGML_PROF_VISIT0_INJ = 1,
+    SGML_PROF_VISIT0 = 2,
+    SGML_PROF_CYCLE_END = 3,
+    SGML_PROF_VISIT0_END = 4
+};
 typedef struct {
     int status;                     /* same value as returned */
     int cycles;                     /* cycles run */
@@ -158,8 +164,11 @@ typedef struct {
      * kernels by class: SGML_PROF_SWEEP0 one relaxation per launch;
      * SGML_PROF_VISIT0_INJ / SGML_PROF_VISIT0 fused visits (interpolation
      * prologue, several relaxations) with / without the injection epilogue;
-     * SGML_PROF_CYCLE_END the cycle-end pass (residual recurrence).  At most
-     * 32 launches of a cycle are timed; prof_untimed counts the others. */
+     * SGML_PROF_CYCLE_END the cycle-end pass (residual recurrence);
+     * SGML_PROF_VISIT0_END the cycle's closing level-0 visit and the cycle
+     * end in one pass (2D mixed-precision cycles after the first, constant
+     * coefficient).  At most 32 launches of a cycle are timed; prof_untimed
+     * counts the others. */
     int prof_launches[SGML_PROF_CLASSES];
     float prof_ms[SGML_PROF_CLASSES];
     int prof_sweeps[SGML_PROF_CLASSES];

@@ -171,6 +171,19 @@ bool launch_coarse_lds(const Variant &v, const LdsOp *ops, int nops, int hdr_off
 template <typename T>
 void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
 
+// The closing visit of a 2D level 0 (interpolation, sweeps relaxations, no
+// injection, not the level's first visit of the cycle) fused with the cycle
+// end (FP32 cycles after the first, constant coefficient, the level-1
+// restriction written: c.g1 and c.s_out set).
+template <typename T>
+void launch_visit_end2d(const Variant &v, const VisitArgs &a, const CycleEndArgs &c, hipStream_t st);
+bool visit_end_supported(int sweeps);
+
+// One restriction step (Algorithm 1) of a 2D level of mc >= 65 coarse nodes
+// per axis, row-marching.
+template <typename T>
+void launch_restrict2d(int mc, const T *fine, T *coarse, hipStream_t st);
+
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st);
 

@@ -1106,6 +1106,12 @@ void launch_inject(int dim, int mc, const T *ef, T *ec, hipStream_t st)
 template <typename Tin, typename Tout>
 void launch_restrict(int dim, int mc, const Tin *fine, Tout *coarse, hipStream_t st)
 {
+    if constexpr (std::is_same<Tin, Tout>::value) {
+        if (dim == 2 && mc >= 65) {
+            launch_restrict2d<Tin>(mc, fine, coarse, st);
+            return;
+        }
+    }
     if (dim == 2)
         hipLaunchKernelGGL((k_restrict<Tin, Tout, 2>), grid_of(2, mc), block_of(), 0, st, fine, coarse, mc);
     else

@@ -698,8 +698,12 @@ sgml_status upload_ops(sgml_plan *P, std::vector<HostOp> &ops, const void *live_
 // Enqueue one cycle: runs of coarse operations as one k_coarse launch each,
 // the rest as grid launches; level-0 relaxations timed when profiling.
 template <typename T>
-sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *G, bool profile,
-                    bool use_sweep3d, int chunk, int zreq, std::vector<Timed> &timed, hipStream_t st)
+// ops [0, end) of the cycle; the level-0 source src0 of the compiled list
+// is read from src0_now (the mixed 2D cycle alternates it between two
+// buffers, the cycle end writing the next cycle's into the other one).
+sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, size_t end, const void *src0, const void *src0_now,
+                    const double *G, bool profile, bool use_sweep3d, int chunk, int zreq, std::vector<Timed> &timed,
+                    hipStream_t st)
 {
     const CoarseOp *dev_ops = P->at<CoarseOp>(P->lay.ops);
     const Level *dev_levels = P->at<Level>(P->lay.levels);
@@ -707,7 +711,7 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
     const LdsXfer *dev_xfer = P->at<LdsXfer>(P->lay.xfer);
     unsigned long long *targets = target(P, 0);
     size_t run = 0;
-    for (size_t i = 0; i < ops.size();) {
+    for (size_t i = 0; i < end;) {
         if (ops[i].coarse) {
             size_t j = i;
             while (j < ops.size() && ops[j].coarse) ++j;
@@ -723,6 +727,7 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, const double *
         const CoarseOp &o = ops[i].op;
         if (o.kind == kOpVisit) {
             VisitArgs a = ops[i].visit;
+            if (a.g == src0) a.g = src0_now;
             a.chunk = chunk;
             a.G = G;
             a.targets = targets;
@@ -833,6 +838,7 @@ struct Solve {
     double norm0 = 0.0;
     double *s = nullptr, *s_next = nullptr, *part = nullptr, *means = nullptr;
     T *shat = nullptr, *g1 = nullptr;
+    T *shat2 = nullptr;  // the other level-0 source buffer (2D mixed, level-1 restriction fused)
     const T *src0 = nullptr, *e = nullptr;
     sgml_status status = SGML_E_MAXCYCLES;
 
@@ -890,9 +896,19 @@ struct Solve {
         // new source to level 1; it then writes the residual to the other buffer
         g1 = mixed && row_march && P->n >= 2 ? P->at<T>(P->lay.g[1]) : nullptr;
         s_next = g1 ? P->at<double>(P->lay.s2) : s;
+        // with the level-1 restriction fused, the next source goes to the other
+        // source buffer (the closing visit may read the current one while the
+        // cycle end writes it): the FP32 half left free by the level-0 buffers
+        // (FP64-sized) after the two FP32 ones
+        if (g1) shat2 = reinterpret_cast<T *>(P->at<char>(P->lay.e0) + 2 * P->M * sizeof(T));
         e = compile_cycle<T>(P, src0, lev, cnt, o->record_pres != 0, coarse_level_of(P, o->coarse_nodes),
                              o->fuse < 0 ? 0 : (o->fuse == 0 ? kDefaultFuseMin : std::max(o->fuse, 64)),
                              g1 != nullptr, ops, updates_per_cycle);
+        // the two buffers alternate only where every reader of the level-0
+        // source is a row-marching visit, which takes it per cycle
+        for (const HostOp &h : ops)
+            if ((h.coarse || h.op.kind != kOpVisit) && (h.op.in0 == src0 || h.op.in1 == src0 || h.op.in2 == src0))
+                shat2 = nullptr;
         rc = upload_ops<T>(P, ops, e, st);
         if (rc != SGML_OK) return rc;
         chunk = o->chunk_rows > 0 ? std::max(8, o->chunk_rows) : 0;  // 0: per launch
@@ -921,7 +937,26 @@ struct Solve {
         if (o->record_pres) clear_targets(P, kPres, (int)lev.size(), q);
         timed.clear();
         P->pev_used = 0;
-        sgml_status rc = run_ops<T>(P, ops, Gc, o->profile != 0, o->fuse >= 0, chunk, zreq, timed, q);
+        // the cycle's closing level-0 visit and the cycle end in one pass: FP32
+        // cycles without Dirichlet data to impose, a constant coefficient, the
+        // level-1 restriction fused, nothing recorded per visit
+        const HostOp *last = ops.empty() ? nullptr : &ops.back();
+        bool fuse_end = false;
+        if constexpr (mixed) {
+            fuse_end = row_march && g1 && shat2 && !Gc && !P->var.sigma && !o->record_pres && last && !last->coarse &&
+                       last->op.kind == kOpVisit && last->op.level == 0 && last->visit.prolong &&
+                       !last->visit.first && !last->visit.inject && visit_end_supported(last->visit.sweeps);
+        }
+        // this cycle's level-0 source and the buffer of the next one (they swap
+        // with the residual buffers)
+        T *src_now = shat, *src_next = shat;
+        if (shat2) {
+            const bool first_slot = s == P->at<double>(P->lay.s);
+            src_now = first_slot ? shat : shat2;
+            src_next = first_slot ? shat2 : shat;
+        }
+        sgml_status rc = run_ops<T>(P, ops, ops.size() - (fuse_end ? 1 : 0), src0, mixed ? src_now : src0, Gc,
+                                    o->profile != 0, o->fuse >= 0, chunk, zreq, timed, q);
         if (rc != SGML_OK) return rc;
         const long ev = o->profile ? prof_pair(P) : -1;
         if (ev >= 0) SGML_HIP(hipEventRecord(P->pev[ev], q));
@@ -936,23 +971,35 @@ struct Solve {
             ca.u = u;
             ca.s = s;
             ca.s_out = s_next;
-            ca.shat = shat;
+            ca.shat = src_next;
             ca.shat_scale = sscale;
             ca.norm = target(P, 0);
             ca.g1 = g1;
             ca.L = L0;
             ca.chunk = chunk;
             ca.zchunk = zreq;
-            if (z_march)
+            if (fuse_end) {
+                if constexpr (mixed) {
+                    VisitArgs a = last->visit;
+                    if (a.g == src0) a.g = src_now;
+                    a.chunk = chunk;
+                    a.G = nullptr;
+                    a.targets = target(P, 0);
+                    a.L = L0;
+                    launch_visit_end2d<T>(P->var, a, ca, q);
+                }
+            } else if (z_march) {
                 launch_cycle_end3d<T>(P->var, ca, q);
-            else
+            } else {
                 launch_cycle_end2d<T>(P->var, ca, q);
+            }
         } else {
             launch_boundary<T>(P->var, L0, e, escale, Gc, P->sigma, u, s, shat, sscale, target(P, 0), q);
         }
         if (ev >= 0) {
             SGML_HIP(hipEventRecord(P->pev[ev + 1], q));
-            timed.push_back({SGML_PROF_CYCLE_END, 0, ev});
+            timed.push_back({fuse_end ? SGML_PROF_VISIT0_END : SGML_PROF_CYCLE_END,
+                             fuse_end ? last->visit.sweeps : 0, ev});
         }
         if (pure) {
             // s - dL(e - mean e) = s - dL e + a mean e differs from s - dL e by a

@@ -6,4 +6,6 @@ namespace sgml {
 
 template void launch_visit2d_r<float, 1>(const VisitArgs &, bool, hipStream_t);
 
+template void launch_visit_end2d_r<float, 1>(const VisitArgs &, const CycleEndArgs &, hipStream_t);
+
 }  // namespace sgml

@@ -8,5 +8,6 @@ namespace sgml {
 template void launch_cycle_end2d<double>(const Variant &, const CycleEndArgs &, hipStream_t);
 template void launch_visit2d<double>(const Variant &, const VisitArgs &, hipStream_t);
 template void launch_visit2d_r<double, 0>(const VisitArgs &, bool, hipStream_t);
+template void launch_restrict2d<double>(int, const double *, double *, hipStream_t);
 
 }  // namespace sgml

@@ -698,6 +698,326 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     if (lane == 0 && nb) atomicMax(A.norm + (size_t)(wid % kRedSlots) * kRedStride, nb);
 }
 
+// The closing visit of level 0 fused with the end of the cycle (FP32 cycles,
+// constant coefficient, every cycle after the first): the visit's row
+// pipeline (interpolation, S relaxations) feeds, instead of a store of e, one
+// more stage that forms dL e in FP64 on a three-row window of the final e,
+// updates u and the residual (written to s_out, s is only read), writes the
+// next cycle's source and, RES, its restriction to level 1 -- what
+// k_cycle_end2d does, on the same values in the same order, without the
+// round trip of e through memory.  The strip's halo is two columns wider than
+// the visit's (the operator's and the restriction's neighbour), and the chunk
+// reads three more rows (the final e from row y0 - 2 to y1, the next source
+// from row y0 - 1).
+template <typename T, int RAD, int S>
+__global__ __launch_bounds__(kVisitBlock) void k_visit_end2d(VisitArgs A, CycleEndArgs C)
+{
+    constexpr int PRO = 1;
+    constexpr int HXV = (S + PRO + 1) / 2 * 2;  // the visit's halo
+    constexpr int HX = HXV + 2;                 // columns a wavefront does not own, each side
+    constexpr int W = 128 - 2 * HX;
+    const Level L = A.L;
+    const int m = L.m;
+    const int lane = threadIdx.x & 63;
+    const int strips = (m + W - 1) / W;
+    const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = wid % strips, sy = wid / strips;
+    const int y0 = sy * A.chunk;
+    if (y0 >= m) return;
+    const int y1 = min(m, y0 + A.chunk);
+    const bool ydir_rows = ((L.dir & 4u) && y0 <= S + 2) || ((L.dir & 8u) && y1 + S + 1 >= m);
+    const int xa = sx * W - HX + 2 * lane;  // even
+    const int xma = mir(xa, m), xmb = mir(xa + 1, m);
+    const bool lane_out = lane >= HX / 2 && lane < (HX + W) / 2;
+    const bool outa = lane_out && xa < m, outb = lane_out && xa + 1 < m;
+
+    RelaxK<T> K;
+    K.scale = (T)L.scale;
+    K.a = (T)L.a;
+    K.theta = (T)L.theta;
+    {
+        const double Wd = RAD ? 6.0 : 4.0, D = Wd * L.scale - L.a;
+        K.omt = (T)(1.0 - L.theta);
+        K.beta = (T)(L.theta * L.scale / D);
+        K.gamma = (T)(L.theta / D);
+        K.aw = (T)(L.a - Wd * L.scale);
+    }
+    const bool xda = ((L.dir & 1u) && xma == 0) || ((L.dir & 2u) && xma == m - 1);
+    const bool xdb = ((L.dir & 1u) && xmb == 0) || ((L.dir & 2u) && xmb == m - 1);
+    const T oma = xda ? T(1) : K.omt, omb = xdb ? T(1) : K.omt;
+    const T bea = xda ? T(0) : K.beta, beb = xdb ? T(0) : K.beta;
+    const T gama = xda ? T(0) : K.gamma, gamb = xdb ? T(0) : K.gamma;
+    const double scale = L.scale, a = L.a, escale = C.escale;
+    const double *__restrict__ sres = C.s;
+    double *__restrict__ sout = C.s_out;
+    double *__restrict__ u = C.u;
+    T *__restrict__ shat = (T *)C.shat;
+    T *__restrict__ g1 = (T *)C.g1;
+    const int m1 = (m + 1) / 2;
+    const int r_first = max(y0 - 1, 0);
+
+    T wa[S][3], wb[S][3];
+    T gha[S + 1], ghb[S + 1];
+#pragma unroll
+    for (int s = 0; s < S; ++s) wa[s][0] = wa[s][1] = wa[s][2] = wb[s][0] = wb[s][1] = wb[s][2] = T(0);
+#pragma unroll
+    for (int k = 0; k < S + 1; ++k) gha[k] = ghb[k] = T(0);
+    double Ea[3] = {0.0, 0.0, 0.0}, Eb[3] = {0.0, 0.0, 0.0};  // final e at rows ro - 2, ro - 1, ro
+    T Ha[3] = {T(0), T(0), T(0)}, Hb[3] = {T(0), T(0), T(0)};  // next source at rows rc - 2 .. rc
+    unsigned long long nb = 0;
+
+    const int r0 = y0 - S - 2;
+    const int rows = (y1 - y0) + 2 * S + 3;
+    unsigned ymask = 0;
+    struct Row {
+        RowIn2<T> v;
+        double ua, ub, sa, sb;  // u and s at row rho - S - 1
+    };
+    auto step_row = [&](const Row &R, int t, auto odd, auto fast) __attribute__((always_inline)) {
+        constexpr bool FAST = decltype(fast)::value;
+        const int rho = r0 + t;
+        const int rm = mir(rho, m);
+        T va, vb;
+        prolonged2<T, decltype(odd)::value>(R.v, va, vb);
+#pragma unroll
+        for (int k = S; k > 0; --k) {
+            gha[k] = gha[k - 1];
+            ghb[k] = ghb[k - 1];
+        }
+        if (FAST) {
+            gha[0] = gama * R.v.ga;
+            ghb[0] = gamb * R.v.gb;
+        } else {
+            gha[0] = K.gamma * R.v.ga;
+            ghb[0] = K.gamma * R.v.gb;
+            ymask = (ymask << 1) | (unsigned)(((L.dir & 4u) && rm == 0) || ((L.dir & 8u) && rm == m - 1));
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            wa[s][0] = wa[s][1];
+            wa[s][1] = wa[s][2];
+            wa[s][2] = va;
+            wb[s][0] = wb[s][1];
+            wb[s][1] = wb[s][2];
+            wb[s][2] = vb;
+            if (FAST) {
+                relax2_fast<T, RAD>(wa[s], wb[s], gha[s + 1], ghb[s + 1], oma, omb, bea, beb, va, vb);
+            } else {
+                const bool yd = (ymask >> (s + 1)) & 1u;
+                const T one[3] = {T(1), T(1), T(1)};
+                T resa, resb;
+                relax2<T, RAD, 0, 0>(wa[s], wb[s], one, one, gha[s + 1], ghb[s + 1], xda || yd, xdb || yd, T(0),
+                                     T(0), K, va, vb, resa, resb);
+            }
+        }
+        // final e at row ro = rho - S, in FP64 (Dirichlet nodes hold zero after the first cycle)
+        Ea[0] = Ea[1];
+        Ea[1] = Ea[2];
+        Ea[2] = escale * (double)va;
+        Eb[0] = Eb[1];
+        Eb[1] = Eb[2];
+        Eb[2] = escale * (double)vb;
+        const int rc = rho - S - 1;
+        // dL e at row rc, both columns (all lanes: cross-lane moves)
+        const double ca = Ea[1], cb = Eb[1];
+        const double la = from_left(cb), rb = from_right(ca);
+        double acca = (la - ca) + (cb - ca) + (Ea[0] - ca) + (Ea[2] - ca);
+        double accb = (ca - cb) + (rb - cb) + (Eb[0] - cb) + (Eb[2] - cb);
+        if (RAD) {
+            const double nla = from_left(Eb[0]), sla = from_left(Eb[2]);
+            const double nrb = from_right(Ea[0]), srb = from_right(Ea[2]);
+            acca += 0.5 * ((nla - ca) + (Eb[0] - ca) + (sla - ca) + (Eb[2] - ca));
+            accb += 0.5 * ((Ea[0] - cb) + (nrb - cb) + (Ea[2] - cb) + (srb - cb));
+        }
+        const double Lea = scale * acca + a * ca, Leb = scale * accb + a * cb;
+        const bool ydir = ((L.dir & 4u) && rc == 0) || ((L.dir & 8u) && rc == m - 1);
+        const bool dira = xda || ydir, dirb = xdb || ydir;
+        const double sna = dira ? 0.0 : R.sa - Lea, snb = dirb ? 0.0 : R.sb - Leb;
+        const T sha = (T)(sna * C.shat_scale), shb = (T)(snb * C.shat_scale);
+        // the next source's window shifts on every row (so that it rotates by
+        // renaming); rows before r_first are never read from it
+        Ha[0] = Ha[1];
+        Ha[1] = Ha[2];
+        Ha[2] = sha;
+        Hb[0] = Hb[1];
+        Hb[1] = Hb[2];
+        Hb[2] = shb;
+        if (t < 2 * S + 2 || rc < r_first || rc >= y1) return;  // uniform: rows outside the chunk
+        if (rc >= y0) {
+            const unsigned q = (unsigned)rc * (unsigned)m + (unsigned)xa;
+            if (outa) {
+                st(u, q, R.ua + ca);
+                st(sout, q, sna);
+                st(shat, q, sha);
+                if (!dira) {
+                    const unsigned long long bb = dbits(sna);
+                    nb = bb > nb ? bb : nb;
+                }
+            }
+            if (outb) {
+                st(u, q + 1u, R.ub + cb);
+                st(sout, q + 1u, snb);
+                st(shat, q + 1u, shb);
+                if (!dirb) {
+                    const unsigned long long bb = dbits(snb);
+                    nb = bb > nb ? bb : nb;
+                }
+            }
+        }
+        // level-1 row J of the next source: fine rows 2J - 1 .. 2J + 1 (images at the faces)
+        int J = -1;
+        T upa = Ha[0], mida = Ha[1], dna = Ha[2], upb = Hb[0], midb = Hb[1], dnb = Hb[2];
+        if ((rc & 1) && rc - 1 >= y0) {
+            J = (rc - 1) / 2;
+            if (rc == 1) {
+                upa = dna;
+                upb = dnb;
+            }
+        } else if (!(rc & 1) && rc == m - 1) {
+            J = rc / 2;
+            upa = Ha[1];
+            mida = Ha[2];
+            dna = Ha[1];
+            upb = Hb[1];
+            midb = Hb[2];
+            dnb = Hb[1];
+        }
+        if (J >= 0) {
+            const T vva = T(0.5) * upa + mida + T(0.5) * dna;
+            const T vvb = T(0.5) * upb + midb + T(0.5) * dnb;
+            const T vl = from_left(vvb);
+            const T res = (T(0.5) * vl + vva + T(0.5) * vvb) * T(0.25);
+            if (outa) st(g1, (unsigned)J * (unsigned)m1 + (unsigned)(xa >> 1), res);
+        }
+    };
+    constexpr int B = 3;
+    Row qa[B], qb[B];
+    auto load_batch = [&](Row(&q)[B], int t0, auto k0) __attribute__((always_inline)) {
+        constexpr int K0 = decltype(k0)::value;
+        unroll<B>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            int t = t0 + k;
+            if (t > rows - 1) t -= 2 * ((t - rows + 2) >> 1);
+            const int rho = r0 + t;
+            load_row2<T, PRO, 0, false, ((S + K0 + k) & 1) != 0>(q[k].v, A, xma, xmb, rho, m);
+            const unsigned rc = (unsigned)min(max(rho - S - 1, 0), m - 1) * (unsigned)m;
+            q[k].ua = ld((const double *)u, rc + (unsigned)xma);
+            q[k].ub = ld((const double *)u, rc + (unsigned)xmb);
+            q[k].sa = ld(sres, rc + (unsigned)xma);
+            q[k].sb = ld(sres, rc + (unsigned)xmb);
+        });
+    };
+    using K0a = std::integral_constant<int, 0>;
+    using K0b = std::integral_constant<int, B>;
+    auto step_batch = [&](const Row(&q)[B], int t0, auto k0, auto fast, bool guard) __attribute__((always_inline)) {
+        constexpr int K0 = decltype(k0)::value;
+        unroll<B>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            if (!guard || t0 + k < rows)
+                step_row(q[k], t0 + k, std::integral_constant<bool, ((S + K0 + k) & 1) != 0>(), fast);
+        });
+    };
+    auto march = [&](auto fast) __attribute__((always_inline)) {
+        load_batch(qa, 0, K0a());
+        int t0 = 0;
+        for (; t0 + 2 * B < rows; t0 += 2 * B) {
+            load_batch(qb, t0 + B, K0b());
+            step_batch(qa, t0, K0a(), fast, false);
+            load_batch(qa, t0 + 2 * B, K0a());
+            step_batch(qb, t0 + B, K0b(), fast, false);
+        }
+        if (t0 + B < rows) load_batch(qb, t0 + B, K0b());
+        step_batch(qa, t0, K0a(), fast, true);
+        step_batch(qb, t0 + B, K0b(), fast, true);
+    };
+    // chunks that read a Dirichlet row take the per-node select of the relaxation
+    if (ydir_rows)
+        march(std::false_type());
+    else
+        march(std::true_type());
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(nb, off, 64);
+        nb = o > nb ? o : nb;
+    }
+    if (lane == 0 && nb) atomicMax(C.norm + (size_t)(wid % kRedSlots) * kRedStride, nb);
+}
+
+// One restriction step (Algorithm 1, eq. (3)) of a 2D level, row-marching:
+// coarse node (I, J) = 1/4 of the sum over fine rows 2J - 1 .. 2J + 1 and
+// columns 2I - 1 .. 2I + 1 of the tensor weights (1/2, 1, 1/2)^2 times the
+// fine values, images outside the grid, accumulated row by row in the order
+// of the per-node kernel (so the results are the same).  Lane l of a
+// wavefront holds coarse column X = x0 - 1 + l and loads fine columns 2X and
+// 2X + 1; 2X - 1 is the previous lane's 2X + 1 (lane 0 is that halo, 63
+// columns written).  The wavefront marches down a chunk of coarse rows,
+// loading each fine row once (the odd row below a coarse row is the odd row
+// above the next), two coarse rows per turn with the next turn's rows in
+// flight.
+template <typename T>
+__global__ __launch_bounds__(kVisitBlock) void k_restrict2d(const T *__restrict__ fine, T *__restrict__ coarse, int mc,
+                                                         int chunk)
+{
+    const int mf = 2 * mc - 1;
+    const int lane = threadIdx.x & 63;
+    const int strips = (mc + 62) / 63;
+    const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = wid % strips, sy = wid / strips;
+    const int J0 = sy * chunk;
+    if (J0 >= mc) return;
+    const int J1 = min(mc, J0 + chunk);
+    const int X = sx * 63 - 1 + lane;
+    const bool out = lane >= 1 && X < mc;
+    const unsigned ca = (unsigned)mir(min(2 * X, 2 * mf - 2), mf), cb = (unsigned)mir(min(2 * X + 1, 2 * mf - 2), mf);
+    struct Rows {
+        T a0, b0, a1, b1;  // fine rows 2J and 2J + 1, columns 2X and 2X + 1
+    };
+    auto load = [&](Rows &R, int J) __attribute__((always_inline)) {
+        const unsigned r0 = (unsigned)mir(2 * J, mf) * (unsigned)mf, r1 = (unsigned)mir(2 * J + 1, mf) * (unsigned)mf;
+        R.a0 = ld(fine, r0 + ca);
+        R.b0 = ld(fine, r0 + cb);
+        R.a1 = ld(fine, r1 + ca);
+        R.b1 = ld(fine, r1 + cb);
+    };
+    // fine row 2J - 1 at columns 2X - 1, 2X, 2X + 1
+    T ul, ua, ub;
+    {
+        const unsigned r = (unsigned)mir(2 * J0 - 1, mf) * (unsigned)mf;
+        ua = fresh(ld(fine, r + ca));
+        ub = fresh(ld(fine, r + cb));
+        ul = from_left(ub);
+    }
+    auto step = [&](const Rows &R, int J) __attribute__((always_inline)) {
+        const T ml = from_left(R.b0), dl = from_left(R.b1);
+        T acc = T(0);
+        acc += T(0.25) * ul;
+        acc += T(0.5) * ua;
+        acc += T(0.25) * ub;
+        acc += T(0.5) * ml;
+        acc += T(1) * R.a0;
+        acc += T(0.5) * R.b0;
+        acc += T(0.25) * dl;
+        acc += T(0.5) * R.a1;
+        acc += T(0.25) * R.b1;
+        if (out && J < J1) st(coarse, (unsigned)J * (unsigned)mc + (unsigned)X, acc / T(4));
+        ul = dl;
+        ua = fresh(R.a1);
+        ub = fresh(R.b1);
+    };
+    Rows qa, qb;
+    load(qa, J0);
+    int J = J0;
+    for (; J + 2 < J1; J += 2) {
+        load(qb, J + 1);
+        step(qa, J);
+        load(qa, J + 2);
+        step(qb, J + 1);
+    }
+    if (J + 1 < J1) load(qb, J + 1);
+    step(qa, J);
+    if (J + 1 < J1) step(qb, J + 1);
+}
+
 // Rows per wavefront: short chunks give more wavefronts (the row chain of a
 // wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
 // Short visits take short chunks: 8 rows (1% faster solves than 16, 24 or
@@ -780,6 +1100,62 @@ void launch_rs(const VisitArgs &a, hipStream_t st)
 }  // namespace
 
 
+// The fused closing visit and cycle end: chunks sized like the long visits
+// (one resident round of wavefronts of this kernel).
+template <typename T, int RAD, int S>
+long long visit_end_resident_waves()
+{
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_visit_end2d<T, RAD, S>, kVisitBlock, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            b = 0;
+        }
+        return b;
+    }();
+    return (long long)per_cu * device_cus() * (kVisitBlock / 64);
+}
+
+template <typename T, int RAD, int S>
+void launch_visit_end_s(const VisitArgs &a0, const CycleEndArgs &c, hipStream_t st)
+{
+    VisitArgs a = a0;
+    const int m = a.L.m;
+    constexpr int W = 128 - 2 * ((S + 2) / 2 * 2 + 2);
+    const int strips = (m + W - 1) / W;
+    if (a0.chunk <= 0 && S >= 4) a.chunk = chunk_rows(0, m, strips, S, visit_end_resident_waves<T, RAD, S>());
+    else a.chunk = chunk_rows(a0.chunk, m, strips, S, 0);
+    a.chunk += a.chunk & 1;
+    const long long waves = (long long)strips * ((m + a.chunk - 1) / a.chunk);
+    const unsigned blocks = (unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64));
+    hipLaunchKernelGGL((k_visit_end2d<T, RAD, S>), dim3(blocks), dim3(kVisitBlock), 0, st, a, c);
+}
+
+template <typename T, int RAD>
+void launch_visit_end_r(const VisitArgs &a, const CycleEndArgs &c, hipStream_t st)
+{
+    switch (a.sweeps) {
+    case 1: launch_visit_end_s<T, RAD, 1>(a, c, st); break;
+    case 2: launch_visit_end_s<T, RAD, 2>(a, c, st); break;
+    case 4: launch_visit_end_s<T, RAD, 4>(a, c, st); break;
+    default: launch_visit_end_s<T, RAD, 6>(a, c, st); break;
+    }
+}
+
+// One row-marching restriction step of a 2D level of mc >= 65 coarse nodes
+// per axis: chunks of coarse rows sized for about 8192 wavefronts (short
+// chains: the pass is latency bound below a few million nodes).
+template <typename T>
+void launch_restrict2d(int mc, const T *fine, T *coarse, hipStream_t st)
+{
+    const long long strips = (mc + 62) / 63;
+    int chunk = (int)((mc * strips + 8191) / 8192);
+    chunk = std::max(4, chunk + (chunk & 1));
+    const long long waves = strips * ((mc + chunk - 1) / chunk);
+    const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
+    hipLaunchKernelGGL((k_restrict2d<T>), grid, block, 0, st, fine, coarse, mc, chunk);
+}
+
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st)
 {
@@ -826,6 +1202,23 @@ void launch_visit2d_r(const VisitArgs &a, bool sigma, hipStream_t st)
     else
         launch_rs<T, RAD, 0>(a, st);
 }
+template <typename T, int RAD>
+void launch_visit_end2d_r(const VisitArgs &a, const CycleEndArgs &c, hipStream_t st)
+{
+    launch_visit_end_r<T, RAD>(a, c, st);
+}
+extern template void launch_visit_end2d_r<float, 0>(const VisitArgs &, const CycleEndArgs &, hipStream_t);
+extern template void launch_visit_end2d_r<float, 1>(const VisitArgs &, const CycleEndArgs &, hipStream_t);
+
+template <typename T>
+void launch_visit_end2d(const Variant &v, const VisitArgs &a, const CycleEndArgs &c, hipStream_t st)
+{
+    if (v.radial)
+        launch_visit_end2d_r<T, 1>(a, c, st);
+    else
+        launch_visit_end2d_r<T, 0>(a, c, st);
+}
+
 extern template void launch_visit2d_r<float, 0>(const VisitArgs &, bool, hipStream_t);
 extern template void launch_visit2d_r<float, 1>(const VisitArgs &, bool, hipStream_t);
 extern template void launch_visit2d_r<double, 0>(const VisitArgs &, bool, hipStream_t);

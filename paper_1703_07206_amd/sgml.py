@@ -21,8 +21,8 @@ FP64, MIXED = 0, 1
 SCHEDULE_ONCE, SCHEDULE_EACH = 0, 1
 HIST = 512
 MAX_VISITS = 128
-PROF_CLASSES = 4
-PROF_NAMES = ("sweep0", "visit0_inject", "visit0", "cycle_end")
+PROF_CLASSES = 5
+PROF_NAMES = ("sweep0", "visit0_inject", "visit0", "cycle_end", "visit0_end")
 
 
 class Problem(ctypes.Structure):

@@ -136,6 +136,13 @@ typedef struct {
                          solves with the same options, output and coefficient;
                          < 0: every launch issued one by one.  Profiled solves
                          never use graphs. */
+    int fuse_end;     /* 2D FP32 cycles with a constant coefficient: the cycle's
+                         closing level-0 visit and the cycle end run as one pass
+                         in every cycle without Dirichlet data to impose and
+                         nothing recorded per visit; 0: default, on levels large
+                         enough for the pass to be bound by memory traffic (4097^2
+                         and above at n_r = 2), > 0: on every level where it
+                         applies, < 0: never.  The results are the same. */
 } sgml_opts;
 
 #define SGML_HIST 512

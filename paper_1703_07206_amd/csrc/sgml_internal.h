@@ -177,7 +177,7 @@ void launch_visit2d(const Variant &v, const VisitArgs &a, hipStream_t st);
 // restriction written: c.g1 and c.s_out set).
 template <typename T>
 void launch_visit_end2d(const Variant &v, const VisitArgs &a, const CycleEndArgs &c, hipStream_t st);
-bool visit_end_supported(int sweeps);
+bool visit_end_supported(int sweeps, int m, bool any_size);  // m: nodes per axis of level 0
 
 // One restriction step (Algorithm 1) of a 2D level of mc >= 65 coarse nodes
 // per axis, row-marching.

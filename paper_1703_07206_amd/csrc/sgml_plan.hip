@@ -945,7 +945,8 @@ struct Solve {
         if constexpr (mixed) {
             fuse_end = row_march && g1 && shat2 && !Gc && !P->var.sigma && !o->record_pres && last && !last->coarse &&
                        last->op.kind == kOpVisit && last->op.level == 0 && last->visit.prolong &&
-                       !last->visit.first && !last->visit.inject && visit_end_supported(last->visit.sweeps);
+                       !last->visit.first && !last->visit.inject && o->fuse_end >= 0 &&
+                       visit_end_supported(last->visit.sweeps, P->m(0), o->fuse_end > 0);
         }
         // this cycle's level-0 source and the buffer of the next one (they swap
         // with the residual buffers)
@@ -1017,7 +1018,7 @@ struct Solve {
     std::vector<long long> graph_key() const
     {
         return {(long long)sizeof(T),       o->n_r,      o->schedule,         o->record_pres,
-                o->coarse_nodes,            o->fuse,     chunk,               zreq,
+                o->coarse_nodes,            o->fuse,     o->fuse_end,         chunk,               zreq,
                 (long long)(uintptr_t)u,    (long long)(uintptr_t)P->sigma, P->var.sigma,
                 (long long)(uintptr_t)P->ws, (long long)(uintptr_t)s, k0, pure};
     }

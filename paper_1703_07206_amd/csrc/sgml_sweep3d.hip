@@ -396,9 +396,9 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end3d(CycleEndArgs A)
 // relaxation 1 runs on the tile plus a one-node halo of every plane as soon
 // as the input planes below and above it are in LDS, relaxation 2 on the tile
 // itself one plane behind, from relaxation 1's plane; the level is read and
-// written once for both.  Neighbour sums by class (centre, in-plane faces,
-// in-plane corners) are formed once per plane and cell and kept in registers,
-// as in k_sweep3d.
+// written once for both.  Each plane's part in the neighbour sums (as the
+// plane below or above a node, and as its own plane) is formed once per cell;
+// a node carries its partial sum from plane to plane in one register.
 //
 // The input planes (values on the tile plus a two-node halo, source on the
 // relaxation-1 region) travel from global memory straight into a ring of
@@ -459,8 +459,8 @@ __device__ __forceinline__ unsigned long long res_widen(unsigned long long b) { 
 
 // The ring holds NSLOT planes (values on the tile plus halo 2, source on the
 // relaxation-1 region): plane i + 2 is staged while plane i is relaxed, into
-// the slot of plane i - 1.  With three slots and three-plane register windows,
-// the march is unrolled by three so that slots and windows are fixed per copy.
+// the slot of plane i - 1.  With three slots, the march is unrolled by three
+// so that the slots are fixed per copy.
 constexpr int NSLOT = 3, kAhead = NSLOT - 1;
 
 // One tile of the paired relaxation: TWL lanes across (tw <= TWL of them own
@@ -547,30 +547,33 @@ __device__ __forceinline__ void pair3d_tile(T (*ring)[2][kSlotCells], T *s1, con
     const T scale = (T)L.scale, a = (T)L.a, theta = (T)L.theta;
     const T Wc = RAD ? T(6) + T(0.5) * T(12) + T(1.0 / 3.0) * T(8) : T(6);
     const T tD = theta / (scale * Wc - a);
-    // one relaxation from the class sums of planes below (0), at (1) and above (2)
-    auto relax = [&](T c0, T c1, T c2v, T x0v, T x1, T x2, T k0, T k1, T k2, T gv, T &r) {
-        const T uc = c1;
-        const T faces = x1 + (c0 + c2v);
-        T sum = faces;
-        if (RAD) {
-            const T edges = k1 + (x0v + x2);
-            const T corners = k0 + k2;
-            sum = faces + T(0.5) * edges + T(1.0 / 3.0) * corners;
-        }
-        r = scale * (sum - Wc * uc) + a * uc - gv;
+    // one relaxation of a node with centre value uc and neighbour sum nsum
+    auto relax = [&](T uc, T nsum, T gv, T &r) {
+        r = scale * (nsum - Wc * uc) + a * uc - gv;
         return uc + tD * r;
     };
-    auto sums = [&](const T *P, int c, int pitch, T &cc, T &cx, T &ck) {
+    // a plane's part in the neighbour sums, at cell c: its centre value cc, its
+    // weight B as the plane below or above a node (centre, faces / 2, corners
+    // / 3) and C as the node's own plane (faces, corners / 2)
+    auto sums = [&](const T *P, int c, int pitch, T &cc, T &B, T &C) {
         cc = P[c];
-        cx = (P[c - 1] + P[c + 1]) + (P[c - pitch] + P[c + pitch]);
-        if (RAD) ck = (P[c - pitch - 1] + P[c - pitch + 1]) + (P[c + pitch - 1] + P[c + pitch + 1]);
+        const T cx = (P[c - 1] + P[c + 1]) + (P[c - pitch] + P[c + pitch]);
+        if (RAD) {
+            const T ck = (P[c - pitch - 1] + P[c - pitch + 1]) + (P[c + pitch - 1] + P[c + pitch + 1]);
+            B = cc + T(0.5) * cx + T(1.0 / 3.0) * ck;
+            C = cx + T(0.5) * ck;
+        } else {
+            B = cc;
+            C = cx;
+        }
     };
 
-    // three-plane windows of class sums, indexed by plane mod 3 (relative to
-    // the chunk's first input plane)
-    T a_cc[2][3] = {}, a_cx[2][3] = {}, a_ck[2][3] = {};  // input planes at the relaxation-1 cells
-    T b_cc[3] = {}, b_cx[3] = {}, b_ck[3] = {};           // relaxation-1 planes at the own node
-    T g_next = T(0), g_cur = T(0);                        // source at the own node, planes zs and z
+    // per node, carried from plane to plane: the neighbour sum of the node's
+    // own plane and the one below (part), the last plane's B and centre value;
+    // the sum of a node is complete when the plane above arrives
+    T a_part[2] = {}, a_B[2] = {}, a_uc[2] = {};  // relaxation-1 cells (input planes)
+    T b_part = T(0), b_B = T(0), b_uc = T(0);      // own node (relaxation-1 planes)
+    T g_next = T(0), g_cur = T(0);                 // source at the own node, planes zs and z
     RB rb = 0;
 
     const int np = (z1 + 1) - (z0 - 2) + 1;  // input planes of the chunk (>= 5)
@@ -580,15 +583,16 @@ __device__ __forceinline__ void pair3d_tile(T (*ring)[2][kSlotCells], T *s1, con
     // relaxation 1 on plane zi - 1, relaxation 2 on plane zi - 2
     auto step = [&](int it, auto PC) {
         constexpr int P = decltype(PC)::value;                        // it % 3
-        constexpr int Pm1 = (P + 2) % 3, Pm2 = (P + 1) % 3;            // (it - 1) % 3, (it - 2) % 3
+        constexpr int Pm1 = (P + 2) % 3;                               // (it - 1) % 3
         if (it + 1 < np) lds_barrier<LPP>();  // plane it + 1 was issued after plane it
         else lds_barrier<0>();
         const int zi = z0 - 2 + it;
         const T *E = &ring[P][0][0];
+        T ncc[2], nB[2], nC[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             if (k == 1 && !two_s) break;
-            sums(E, sin_c[k], IX, a_cc[k][P], a_cx[k][P], a_ck[k][P]);
+            sums(E, sin_c[k], IX, ncc[k], nB[k], nC[k]);
         }
         const int zs = zi - 1;
         g_cur = g_next;
@@ -603,8 +607,7 @@ __device__ __forceinline__ void pair3d_tile(T (*ring)[2][kSlotCells], T *s1, con
             for (int k = 0; k < 2; ++k) {
                 if (k == 1 && !two_s) break;
                 T r;
-                T v = relax(a_cc[k][Pm2], a_cc[k][Pm1], a_cc[k][P], a_cx[k][Pm2], a_cx[k][Pm1], a_cx[k][P],
-                            a_ck[k][Pm2], a_ck[k][Pm1], a_ck[k][P], S[sidx[k]], r);
+                T v = relax(a_uc[k], a_part[k] + nB[k], S[sidx[k]], r);
                 const bool dir = zd || sdxy[k];
                 if (G) {
                     if (dir) v = (T)G[(size_t)zsm * lam * Nf * Nf + gxy[k]];
@@ -614,27 +617,38 @@ __device__ __forceinline__ void pair3d_tile(T (*ring)[2][kSlotCells], T *s1, con
                 s1[k == 0 ? swr : sidx[1]] = v;
             }
         }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (k == 1 && !two_s) break;
+            a_part[k] = a_B[k] + nC[k];
+            a_B[k] = nB[k];
+            a_uc[k] = ncc[k];
+        }
         lds_barrier<63>();
         // the slot of plane it - 1 is free: stage plane it + 2 there
         if (it + kAhead < np) issue(zi + kAhead, Pm1);
-        if (it >= 2) sums(s1, c2, SX, b_cc[Pm1], b_cx[Pm1], b_ck[Pm1]);  // relaxation-1 plane zs
-        const int z = zs - 1;
-        if (it >= 4 && z < z1) {
-            T r;
-            // relaxation-1 planes z - 1, z, z + 1 have indices it - 3, it - 2, it - 1
-            T v = relax(b_cc[P], b_cc[Pm2], b_cc[Pm1], b_cx[P], b_cx[Pm2], b_cx[Pm1], b_ck[P], b_ck[Pm2],
-                        b_ck[Pm1], g_cur, r);
-            const bool dir = is_dir<3>(x, y, z, m, L.dir);
-            if (G) {
-                if (dir && own) v = (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)];
-            } else {
-                v = dir ? T(0) : v;
+        if (it >= 2) {
+            T bcc, bB, bC;
+            sums(s1, c2, SX, bcc, bB, bC);  // relaxation-1 plane zs
+            const int z = zs - 1;
+            if (it >= 4 && z < z1) {
+                T r;
+                T v = relax(b_uc, b_part + bB, g_cur, r);
+                const bool dir = is_dir<3>(x, y, z, m, L.dir);
+                if (G) {
+                    if (dir && own) v = (T)G[lin(x * L.lam, y * L.lam, z * L.lam, L.N)];
+                } else {
+                    v = dir ? T(0) : v;
+                }
+                if (pres) {
+                    const RB b = res_bits(r);
+                    rb = (own && !dir && b > rb) ? b : rb;
+                }
+                if (own) *(T *)((char *)eout + (size_t)z * plane_bytes + own_off) = v;
             }
-            if (pres) {
-                const RB b = res_bits(r);
-                rb = (own && !dir && b > rb) ? b : rb;
-            }
-            if (own) *(T *)((char *)eout + (size_t)z * plane_bytes + own_off) = v;
+            b_part = b_B + bC;
+            b_B = bB;
+            b_uc = bcc;
         }
     };
     for (int it = 0; it < np; it += 3) {

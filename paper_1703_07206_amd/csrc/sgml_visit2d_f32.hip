@@ -14,6 +14,14 @@ template void launch_restrict2d<float>(int, const float *, float *, hipStream_t)
 
 template void launch_visit_end2d<float>(const Variant &, const VisitArgs &, const CycleEndArgs &, hipStream_t);
 template void launch_visit_end2d_r<float, 0>(const VisitArgs &, const CycleEndArgs &, hipStream_t);
-bool visit_end_supported(int sweeps) { return sweeps == 1 || sweeps == 2 || sweeps == 4 || sweeps == 6; }
+// by default fused where level 0 is large: on smaller levels one wavefront's
+// longer row pipeline, not memory traffic, sets the time of the fused pass
+bool visit_end_supported(int sweeps, int m, bool any_size)
+{
+    if (!(sweeps == 1 || sweeps == 2 || sweeps == 4 || sweeps == 6)) return false;
+    if (any_size) return true;
+    const int W = 128 - 2 * ((sweeps + 2) / 2 * 2 + 2);
+    return (long long)((m + W - 1) / W) * m >= kLargeLevelRows;
+}
 
 }  // namespace sgml

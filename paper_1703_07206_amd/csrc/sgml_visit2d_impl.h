@@ -1018,6 +1018,12 @@ __global__ __launch_bounds__(kVisitBlock) void k_restrict2d(const T *__restrict_
     if (J + 1 < J1) step(qb, J + 1);
 }
 
+// Rows of strips (strips x rows per strip) from which a level is large
+// enough for its visits to be bound by memory traffic rather than by the
+// length of one wavefront's row pipeline (4097^2 and above at six
+// relaxations).
+constexpr long long kLargeLevelRows = 1 << 17;
+
 // Rows per wavefront: short chunks give more wavefronts (the row chain of a
 // wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
 // Short visits take short chunks: 8 rows (1% faster solves than 16, 24 or
@@ -1033,7 +1039,7 @@ __global__ __launch_bounds__(kVisitBlock) void k_restrict2d(const T *__restrict_
 int chunk_rows(int requested, int m, int strips, int sweeps, long long slots)
 {
     if (requested > 0) return requested;
-    if (sweeps < 4 || (long long)strips * m < (1 << 17)) return m <= 1025 ? 4 : 8;
+    if (sweeps < 4 || (long long)strips * m < kLargeLevelRows) return m <= 1025 ? 4 : 8;
     const long long per = slots / strips;  // chunks per strip that fill the slots once
     if (per < 1) return std::min(m, 96);
     return std::max(8, (int)((m + per - 1) / per));

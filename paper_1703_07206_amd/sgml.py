@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
                 ("record_pres", ctypes.c_int), ("profile", ctypes.c_int),
                 ("coarse_nodes", ctypes.c_int), ("stall_window", ctypes.c_int),
                 ("fuse", ctypes.c_int), ("chunk_rows", ctypes.c_int), ("z_chunk", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("fuse_end", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -213,10 +213,10 @@ class Plan:
 
     def opts(self, tol=1e-12, max_cycles=100, n_r=2, schedule=SCHEDULE_ONCE, precision=None,
              record_pres=False, profile=False, coarse_nodes=0, stall_window=0, fuse=0, chunk_rows=0,
-             z_chunk=0, graphs=0):
+             z_chunk=0, graphs=0, fuse_end=0):
         return Opts(tol, max_cycles, n_r, schedule, self.precision if precision is None else precision,
                     int(record_pres), int(profile), int(coarse_nodes), int(stall_window), int(fuse),
-                    int(chunk_rows), int(z_chunk), int(graphs))
+                    int(chunk_rows), int(z_chunk), int(graphs), int(fuse_end))
 
     def solve(self, f, G=None, u=None, raise_on_failure=True, stream=None, **kw):
         """Solve dL(u) = f; returns (u, stats dict)."""

@@ -53,6 +53,29 @@ def test_graph_replays_equal_eager_launches(case):
         assert torch.equal(u2, ref) and st2["pres"] == st3["pres"]
 
 
+@pytest.mark.parametrize("stencil", [AXIS, RADIAL], ids=["axis", "rad"])
+def test_graph_replays_with_fused_cycle_end(stencil):
+    # the closing level-0 visit fused with the cycle end (forced at 513^2)
+    # alternates the FP32 source between two buffers, as the residual: one
+    # graph per buffer; replays equal the eager launches and the unfused cycle
+    from paper_1703_07206_amd import sgml
+    wl = W.random_problem(2, 9, stencil, "DDNN", seed=2450, hetero=False, a=0.0, dirichlet_values=True)
+    plan = sgml.Plan(2, 9, stencil, "DDNN", 0.0, None, precision=sgml.MIXED)
+    f, G = dev(wl.f), dev(wl.G)
+    kw = dict(tol=1e-13, max_cycles=200, precision=sgml.MIXED)
+    ref, st_ref = plan.solve(f, G, graphs=-1, fuse_end=1, **kw)
+    unfused, st_un = plan.solve(f, G, graphs=-1, fuse_end=-1, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, unfused) and st_ref["history"] == st_un["history"]
+    u = torch.empty_like(f)
+    for rep in range(3):
+        u.fill_(float("nan"))
+        _, st = plan.solve(f, G, u, fuse_end=1, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), rep
+        assert st["history"] == st_ref["history"]
+
+
 def test_graph_replays_in_batches():
     from paper_1703_07206_amd import sgml
     wls = [W.random_problem(3, 6, RADIAL, "DDDDDD", seed=2500 + r, hetero=False) for r in range(3)]

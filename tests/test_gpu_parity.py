@@ -264,6 +264,26 @@ def test_fused_visits_match_oracle(case, n_r, sched):
         assert np.max(np.abs(np.array(st1["pres"]) - pres_or)) <= 1e-11 * np.max(pres_or)
 
 
+@pytest.mark.parametrize("case", [FUSED_CASES[0], FUSED_CASES[3]], ids=[FUSED_IDS[0], FUSED_IDS[3]])
+def test_fused_cycle_end_same_results(case):
+    # FP32 cycles with the closing level-0 visit (interpolation and six
+    # relaxations at n_r = 2) and the cycle end in one pass, forced on these
+    # small grids, give the results of the two passes cycle by cycle, and the
+    # oracle's within the FP32 bar
+    dim, n, stencil, faces, hetero, a, with_G = case
+    wl = problem(dim, n, stencil, faces, hetero, a, with_G, seed=1250 + n)
+    u_or, _ = oracle_problem(wl).solve(wl.f, G=wl.G, tol=0.0, max_cycles=3)
+    u1, st1 = gpu_solve(wl, "mixed", tol=0.0, max_cycles=3, fuse_end=1)
+    u0, st0 = gpu_solve(wl, "mixed", tol=0.0, max_cycles=3, fuse_end=-1)
+    assert np.array_equal(u1, u0) and st1["history"] == st0["history"]
+    assert rel_inf(u1, u_or) < 1e-5
+    # the fused pass ran in the cycles after the first (the first imposes G)
+    _, sp = gpu_solve(wl, "mixed", tol=0.0, max_cycles=3, fuse_end=1, profile=True)
+    assert sp["prof"]["visit0_end"]["launches"] == (2 if with_G else 3)
+    _, sp = gpu_solve(wl, "mixed", tol=0.0, max_cycles=3, fuse_end=-1, profile=True)
+    assert sp["prof"]["visit0_end"]["launches"] == 0
+
+
 @pytest.mark.parametrize("case", FUSED_CASES[:2], ids=FUSED_IDS[:2])
 def test_fused_visits_converged(case):
     dim, n, stencil, faces, hetero, a, with_G = case

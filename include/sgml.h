@@ -116,7 +116,8 @@ typedef struct {
                          2D and 3D); values below 64 act as 64 */
     int chunk_rows;   /* rows each wavefront marches through in the 2D row-marching
                          passes; 0: chosen per launch (8 for short visits, 4 on
-                         levels of at most 1025 nodes per axis; for long
+                         levels of at most 1025 nodes per axis, 2 on levels of
+                         at most 257; for long
                          visits of large levels the shortest chunk that keeps every
                          wavefront of the launch resident at once; 96 for the cycle
                          end, fewer on levels too small to fill the device), values

@@ -565,19 +565,25 @@ __global__ __launch_bounds__(kVisitBlock) void k_cycle_end2d(CycleEndArgs A)
     // (s, u).  Every lane and row issues the same loads, from the mirrored
     // column and a row clamped into the grid, so that the compiler waits for
     // each by count at its use and the next batch stays in flight; values
-    // outside the lanes and rows that use them are ignored.
+    // outside the lanes and rows that use them are ignored.  u is read from
+    // the nearest column and row it is written at, s (read also beside the
+    // strip and above the chunk when restricting) from the nearest row it is
+    // used at: the ignored values are cache hits, not fetched from memory.
     struct Raw {
         T e;
         double sg, s, u;
     };
+    const unsigned xum = (unsigned)min(max(x, sx * W), min(sx * W + W, m) - 1);
+    const unsigned xsm = RES ? (unsigned)xm : xum;
     auto load = [&](Raw &R, int t) {
         const int rho = y0 - 1 - RES + t;
         const unsigned rm = (unsigned)mir(rho, m), um = (unsigned)m;
         R.e = ld(E, rm * um + (unsigned)xm);
         if (SIG) R.sg = ld(sig, rm * um + (unsigned)xm);
-        const unsigned rc = (unsigned)min(max(rho - 1, 0), m - 1);
-        R.s = ld(sres, rc * um + (unsigned)xm);
-        R.u = ld((const double *)u, rc * um + (unsigned)xm);
+        const unsigned rs = (unsigned)min(max(rho - 1, r_first), y1 - 1);
+        const unsigned ru = (unsigned)min(max(rho - 1, y0), y1 - 1);
+        R.s = ld(sres, rs * um + xsm);
+        R.u = ld((const double *)u, ru * um + xum);
     };
     auto step_row = [&](const Raw &R, int t, auto hasg) {
         constexpr bool HASG = decltype(hasg)::value;
@@ -755,6 +761,15 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit_end2d(VisitArgs A, CycleE
     T *__restrict__ g1 = (T *)C.g1;
     const int m1 = (m + 1) / 2;
     const int r_first = max(y0 - 1, 0);
+    // u is read only where it is written, s also one row above the chunk and
+    // one column left of the strip (the restriction's neighbours): the other
+    // lanes and rows read the nearest such column pair and row (cache hits,
+    // values unused), so that the loads stay branch-free without fetching
+    // the halo from memory
+    const int xu = sx * W + 2 * min(max(lane - HX / 2, 0), W / 2 - 1);
+    const unsigned xua = (unsigned)min(xu, m - 1), xub = (unsigned)min(xu + 1, m - 1);
+    const bool s_lane = lane >= HX / 2 - 1 && lane < (HX + W) / 2;
+    const unsigned xsa = s_lane ? (unsigned)xma : xua, xsb = s_lane ? (unsigned)xmb : xub;
 
     T wa[S][3], wb[S][3];
     T gha[S + 1], ghb[S + 1];
@@ -900,11 +915,12 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit_end2d(VisitArgs A, CycleE
             if (t > rows - 1) t -= 2 * ((t - rows + 2) >> 1);
             const int rho = r0 + t;
             load_row2<T, PRO, 0, false, ((S + K0 + k) & 1) != 0>(q[k].v, A, xma, xmb, rho, m);
-            const unsigned rc = (unsigned)min(max(rho - S - 1, 0), m - 1) * (unsigned)m;
-            q[k].ua = ld((const double *)u, rc + (unsigned)xma);
-            q[k].ub = ld((const double *)u, rc + (unsigned)xmb);
-            q[k].sa = ld(sres, rc + (unsigned)xma);
-            q[k].sb = ld(sres, rc + (unsigned)xmb);
+            const unsigned ru = (unsigned)min(max(rho - S - 1, y0), y1 - 1) * (unsigned)m;
+            const unsigned rs = (unsigned)min(max(rho - S - 1, r_first), y1 - 1) * (unsigned)m;
+            q[k].ua = ld((const double *)u, ru + xua);
+            q[k].ub = ld((const double *)u, ru + xub);
+            q[k].sa = ld(sres, rs + xsa);
+            q[k].sb = ld(sres, rs + xsb);
         });
     };
     using K0a = std::integral_constant<int, 0>;
@@ -1027,9 +1043,9 @@ constexpr long long kLargeLevelRows = 1 << 17;
 // Rows per wavefront: short chunks give more wavefronts (the row chain of a
 // wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
 // Short visits take short chunks: 8 rows (1% faster solves than 16, 24 or
-// 32), 4 on levels of at most 1025 nodes per axis, which have few wavefronts
-// to spread their latency over (1% faster than 8 on the 4097^2 and 129^2
-// solves).  Long visits on a large level take the shortest chunk for which the
+// 32), 4 on levels of at most 1025 nodes per axis and 2 on levels of at most
+// 257, which have few wavefronts to spread their latency over (each 1% faster
+// on the 4097^2 solves, 3% on the 129^2 ones).  Long visits on a large level take the shortest chunk for which the
 // whole grid is resident at once (slots = resident wavefronts of the chip):
 // one round of workgroups, none waiting for a second.  On the 4097^2 level
 // that is 38 rows in FP32 (4 workgroups per CU) and 75 (76: chunks are
@@ -1039,7 +1055,7 @@ constexpr long long kLargeLevelRows = 1 << 17;
 int chunk_rows(int requested, int m, int strips, int sweeps, long long slots)
 {
     if (requested > 0) return requested;
-    if (sweeps < 4 || (long long)strips * m < kLargeLevelRows) return m <= 1025 ? 4 : 8;
+    if (sweeps < 4 || (long long)strips * m < kLargeLevelRows) return m <= 257 ? 2 : m <= 1025 ? 4 : 8;
     const long long per = slots / strips;  // chunks per strip that fill the slots once
     if (per < 1) return std::min(m, 96);
     return std::max(8, (int)((m + per - 1) / per));

@@ -93,6 +93,21 @@ __device__ __forceinline__ double fresh(double v)
     asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
     return r;
 }
+// The same copy into a register other than the source's (an early-clobber
+// output): a value computed in place in a loaded register (v_fmac on it)
+// moves out of it, which frees that register for the next batch's load.
+__device__ __forceinline__ float fresh_apart(float v)
+{
+    float r;
+    asm("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ double fresh_apart(double v)
+{
+    double r;
+    asm("v_mov_b64 %0, %1" : "=&v"(r) : "v"(v));
+    return r;
+}
 
 // theta / D with D the local diagonal: FP32 uses the hardware reciprocal
 // (the relaxation is the approximate inner solver of the mixed mode), FP64
@@ -180,7 +195,7 @@ __device__ __forceinline__ void prolonged2(const RowIn2<T> &R, T &va, T &vb)
     if (!ODD) {
         const T p = R.c0 - R.sta;
         const T pr = from_right(p);
-        va = fresh(R.c0);  // a window value: not the loaded register (see the delay lines)
+        va = R.c0;
         vb = R.stb + T(0.5) * (p + pr);
     } else {
         const T p0 = R.c0 - R.s0, p1 = R.c1 - R.s1;
@@ -342,9 +357,13 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit2d(VisitArgs A)
         if (PRO) {
             prolonged2<T, decltype(odd)::value>(R, va, vb);
         } else {
-            va = fresh(R.sta);
-            vb = fresh(R.stb);
+            va = R.sta;
+            vb = R.stb;
         }
+        // window values, moved out of the loaded registers (computed in place
+        // there or copies), which the next batch's loads then reuse
+        va = fresh_apart(va);
+        vb = fresh_apart(vb);
 #pragma unroll
         for (int k = S; k > 0; --k) {
             gha[k] = gha[k - 1];
@@ -794,6 +813,8 @@ __global__ __launch_bounds__(kVisitBlock) void k_visit_end2d(VisitArgs A, CycleE
         const int rm = mir(rho, m);
         T va, vb;
         prolonged2<T, decltype(odd)::value>(R.v, va, vb);
+        va = fresh_apart(va);
+        vb = fresh_apart(vb);
 #pragma unroll
         for (int k = S; k > 0; --k) {
             gha[k] = gha[k - 1];

@@ -22,12 +22,6 @@ import time
 
 import numpy as np
 
-# Kernel arguments in device memory rather than host-coherent memory: a cycle
-# issues some 35 small launches, each of which otherwise waits on a host
-# memory read for its arguments.  Read by the HIP runtime at initialisation,
-# so it is set before torch starts HIP; recorded in the output's config.
-os.environ.setdefault("HIP_FORCE_DEV_KERNARG", "1")
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 

@@ -118,8 +118,10 @@ typedef struct {
                          passes; 0: chosen per launch (8 for short visits, 4 on
                          levels of at most 1025 nodes per axis, 2 on levels of
                          at most 257; for long
-                         visits of large levels the shortest chunk that keeps every
-                         wavefront of the launch resident at once; 96 for the cycle
+                         visits of large levels the shortest chunk that fills the
+                         device's wavefront slots for the kernel in one round, half
+                         of them in FP64 and in the fused closing visit; 96 for the
+                         cycle
                          end, fewer on levels too small to fill the device), values
                          below 8 act as 8, odd values are rounded up to even in the
                          visits */

@@ -1063,16 +1063,18 @@ constexpr long long kLargeLevelRows = 1 << 17;
 
 // Rows per wavefront: short chunks give more wavefronts (the row chain of a
 // wavefront is sequential) at the cost of 2S recomputed halo rows per chunk.
-// Short visits take short chunks: 8 rows (1% faster solves than 16, 24 or
-// 32), 4 on levels of at most 1025 nodes per axis and 2 on levels of at most
-// 257, which have few wavefronts to spread their latency over (each 1% faster
-// on the 4097^2 solves, 3% on the 129^2 ones).  Long visits on a large level take the shortest chunk for which the
-// whole grid is resident at once (slots = resident wavefronts of the chip):
-// one round of workgroups, none waiting for a second.  On the 4097^2 level
-// that is 38 rows in FP32 (4 workgroups per CU) and 75 (76: chunks are
-// even) in FP64 (2 per CU,
-// the longer register windows): 69 / 130 us against 77 / 154 us for fixed
-// 48 / 96-row chunks, which leave part of the chip a fourth (third) block.
+// Short visits take short chunks: 8 rows (1% faster solves than 6, 12, 16,
+// 24 or 32), 4 on levels of at most 1025 nodes per axis and 2 on levels of at
+// most 257, which have few wavefronts to spread their latency over (each 1%
+// faster on the 4097^2 solves, 3% on the 129^2 ones).  Long visits on a large
+// level take the shortest chunk for which the launch fills the wavefront
+// slots the chip has for the kernel in one round (slots), no workgroup
+// waiting for a second: all of them in FP32 (38 rows on the 4097^2 level),
+// half of them in FP64 and in the fused closing visit, whose registers allow
+// two wavefronts per SIMD (152 rows, one wavefront per SIMD).  Measured on
+// the 4097^2 solves: the FP64 and mixed solves 1% faster with half the slots,
+// the FP32 visit 1% slower (unfused mixed solve); a third or a quarter of the
+// slots leaves SIMDs idle (mixed solve +13%, +24%).
 int chunk_rows(int requested, int m, int strips, int sweeps, long long slots)
 {
     if (requested > 0) return requested;
@@ -1106,7 +1108,8 @@ void launch_one(const VisitArgs &a0, hipStream_t st)
     const int m = a.L.m;
     constexpr int W = 128 - 2 * ((S + PRO + 1) / 2 * 2);
     const int strips = (m + W - 1) / W;
-    if (a0.chunk <= 0 && S >= 4) a.chunk = chunk_rows(0, m, strips, S, resident_waves<T, RAD, SIG, S, PRO, REC>());
+    if (a0.chunk <= 0 && S >= 4)
+        a.chunk = chunk_rows(0, m, strips, S, resident_waves<T, RAD, SIG, S, PRO, REC>() / (sizeof(T) == 8 ? 2 : 1));
     else a.chunk = chunk_rows(a0.chunk, m, strips, S, 0);
     a.chunk += a.chunk & 1;  // chunks start at even rows: row parity follows from the place in the march
     const long long waves = (long long)strips * ((m + a.chunk - 1) / a.chunk);
@@ -1166,7 +1169,8 @@ void launch_visit_end_s(const VisitArgs &a0, const CycleEndArgs &c, hipStream_t 
     const int m = a.L.m;
     constexpr int W = 128 - 2 * ((S + 2) / 2 * 2 + 2);
     const int strips = (m + W - 1) / W;
-    if (a0.chunk <= 0 && S >= 4) a.chunk = chunk_rows(0, m, strips, S, visit_end_resident_waves<T, RAD, S>());
+    if (a0.chunk <= 0 && S >= 4)
+        a.chunk = chunk_rows(0, m, strips, S, visit_end_resident_waves<T, RAD, S>() / 2);
     else a.chunk = chunk_rows(a0.chunk, m, strips, S, 0);
     a.chunk += a.chunk & 1;
     const long long waves = (long long)strips * ((m + a.chunk - 1) / a.chunk);

@@ -183,6 +183,10 @@ bool visit_end_supported(int sweeps, int m, bool any_size);  // m: nodes per axi
 // per axis, row-marching.
 template <typename T>
 void launch_restrict2d(int mc, const T *fine, T *coarse, hipStream_t st);
+// Two restriction steps in one pass: fine -> coarse (mc >= 65 nodes per axis)
+// -> coarse2 ((mc + 1) / 2 nodes per axis).
+template <typename T>
+void launch_restrict2d2(int mc, const T *fine, T *coarse, T *coarse2, hipStream_t st);
 
 template <typename T>
 void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a, hipStream_t st);

@@ -759,10 +759,16 @@ sgml_status run_ops(sgml_plan *P, const std::vector<HostOp> &ops, size_t end, co
             break;
         }
         case kOpRestrict:
-            if (P->dim == 3 && use_sweep3d && sweep3d_supported(2 * o.m - 1))
+            if (P->dim == 3 && use_sweep3d && sweep3d_supported(2 * o.m - 1)) {
                 launch_restrict3d<T>(o.m, (const T *)o.in0, (T *)o.out, zreq, st);
-            else
+            } else if (P->dim == 2 && use_sweep3d && o.m >= 65 && i + 1 < end && !ops[i + 1].coarse &&
+                       ops[i + 1].op.kind == kOpRestrict && ops[i + 1].op.in0 == o.out) {
+                // this step and the next in one pass
+                launch_restrict2d2<T>(o.m, (const T *)o.in0, (T *)o.out, (T *)ops[i + 1].op.out, st);
+                ++i;
+            } else {
                 launch_restrict<T, T>(P->dim, o.m, (const T *)o.in0, (T *)o.out, st);
+            }
             break;
         case kOpProlong:
             if (P->dim == 3 && use_sweep3d && sweep3d_supported(o.m))

@@ -11,6 +11,7 @@ template void launch_cycle_end2d<float>(const Variant &, const CycleEndArgs &, h
 template void launch_visit2d<float>(const Variant &, const VisitArgs &, hipStream_t);
 template void launch_visit2d_r<float, 0>(const VisitArgs &, bool, hipStream_t);
 template void launch_restrict2d<float>(int, const float *, float *, hipStream_t);
+template void launch_restrict2d2<float>(int, const float *, float *, float *, hipStream_t);
 
 template void launch_visit_end2d<float>(const Variant &, const VisitArgs &, const CycleEndArgs &, hipStream_t);
 template void launch_visit_end2d_r<float, 0>(const VisitArgs &, const CycleEndArgs &, hipStream_t);

@@ -9,5 +9,6 @@ template void launch_cycle_end2d<double>(const Variant &, const CycleEndArgs &, 
 template void launch_visit2d<double>(const Variant &, const VisitArgs &, hipStream_t);
 template void launch_visit2d_r<double, 0>(const VisitArgs &, bool, hipStream_t);
 template void launch_restrict2d<double>(int, const double *, double *, hipStream_t);
+template void launch_restrict2d2<double>(int, const double *, double *, double *, hipStream_t);
 
 }  // namespace sgml

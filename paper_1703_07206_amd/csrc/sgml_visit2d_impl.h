@@ -1055,6 +1055,106 @@ __global__ __launch_bounds__(kVisitBlock) void k_restrict2d(const T *__restrict_
     if (J + 1 < J1) step(qb, J + 1);
 }
 
+// Two restriction steps in one pass: the level of mc nodes per axis
+// (written, as k_restrict2d writes it) and the next coarser one.  Lane l
+// holds column X = x0 - 2 + l of the first, as in k_restrict2d; lane 0 lacks
+// its left fine column and lane 1 is the left neighbour of the strip's first
+// even column, so lanes 2..63 are written (62 columns).  The wavefront
+// marches its chunk of rows from one row above, keeps the last three rows,
+// and each time they are rows 2K - 1, 2K, 2K + 1 (images at the faces) writes
+// row K of the second level at the even columns, summed row by row as the
+// per-node kernel sums, so that both levels are the same as from two
+// k_restrict2d launches.
+template <typename T>
+__global__ __launch_bounds__(kVisitBlock) void k_restrict2d2(const T *__restrict__ fine, T *__restrict__ coarse,
+                                                          T *__restrict__ coarse2, int mc, int chunk)
+{
+    const int mf = 2 * mc - 1, mc2 = (mc + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int strips = (mc + 61) / 62;
+    const int wid = blockIdx.x * (kVisitBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sx = wid % strips, sy = wid / strips;
+    const int J0 = sy * chunk;  // even
+    if (J0 >= mc) return;
+    const int J1 = min(mc, J0 + chunk);
+    const int Js = max(J0 - 1, 0);  // first row computed
+    const int X = sx * 62 - 2 + lane;
+    const bool out = lane >= 2 && X < mc;
+    const bool out2 = out && !(X & 1);
+    const unsigned ca = (unsigned)mir(min(2 * X, 2 * mf - 2), mf), cb = (unsigned)mir(min(2 * X + 1, 2 * mf - 2), mf);
+    struct Rows {
+        T a0, b0, a1, b1;  // fine rows 2J and 2J + 1, columns 2X and 2X + 1
+    };
+    auto load = [&](Rows &R, int J) __attribute__((always_inline)) {
+        const unsigned r0 = (unsigned)mir(2 * J, mf) * (unsigned)mf, r1 = (unsigned)mir(2 * J + 1, mf) * (unsigned)mf;
+        R.a0 = ld(fine, r0 + ca);
+        R.b0 = ld(fine, r0 + cb);
+        R.a1 = ld(fine, r1 + ca);
+        R.b1 = ld(fine, r1 + cb);
+    };
+    // fine row 2J - 1 at columns 2X - 1, 2X, 2X + 1
+    T ul, ua, ub;
+    {
+        const unsigned r = (unsigned)mir(2 * Js - 1, mf) * (unsigned)mf;
+        ua = fresh(ld(fine, r + ca));
+        ub = fresh(ld(fine, r + cb));
+        ul = from_left(ub);
+    }
+    T h0 = T(0), h1 = T(0), h2 = T(0);  // first-level rows J - 2, J - 1, J
+    auto restrict2 = [&](T up, T mid, T dn, int K) __attribute__((always_inline)) {
+        T acc = T(0);
+        acc += T(0.25) * from_left(up);
+        acc += T(0.5) * up;
+        acc += T(0.25) * from_right(up);
+        acc += T(0.5) * from_left(mid);
+        acc += T(1) * mid;
+        acc += T(0.5) * from_right(mid);
+        acc += T(0.25) * from_left(dn);
+        acc += T(0.5) * dn;
+        acc += T(0.25) * from_right(dn);
+        if (out2) st(coarse2, (unsigned)K * (unsigned)mc2 + (unsigned)(X >> 1), acc / T(4));
+    };
+    auto step = [&](const Rows &R, int J) __attribute__((always_inline)) {
+        const T ml = from_left(R.b0), dl = from_left(R.b1);
+        T acc = T(0);
+        acc += T(0.25) * ul;
+        acc += T(0.5) * ua;
+        acc += T(0.25) * ub;
+        acc += T(0.5) * ml;
+        acc += T(1) * R.a0;
+        acc += T(0.5) * R.b0;
+        acc += T(0.25) * dl;
+        acc += T(0.5) * R.a1;
+        acc += T(0.25) * R.b1;
+        const T v = acc / T(4);
+        if (out && J >= J0) st(coarse, (unsigned)J * (unsigned)mc + (unsigned)X, v);
+        ul = dl;
+        ua = fresh(R.a1);
+        ub = fresh(R.b1);
+        h0 = h1;
+        h1 = h2;
+        h2 = v;
+        // second-level row K: rows 2K - 1 (row 1 for K = 0), 2K, 2K + 1 (row
+        // 2K - 1 for the last row)
+        if ((J & 1) && J - 1 >= J0)
+            restrict2(J == 1 ? h2 : h0, h1, h2, (J - 1) / 2);
+        else if (!(J & 1) && J == mc - 1)
+            restrict2(h1, h2, h1, J / 2);
+    };
+    Rows qa, qb;
+    load(qa, Js);
+    int J = Js;
+    for (; J + 2 < J1; J += 2) {
+        load(qb, J + 1);
+        step(qa, J);
+        load(qa, J + 2);
+        step(qb, J + 1);
+    }
+    if (J + 1 < J1) load(qb, J + 1);
+    step(qa, J);
+    if (J + 1 < J1) step(qb, J + 1);
+}
+
 // Rows of strips (strips x rows per strip) from which a level is large
 // enough for its visits to be bound by memory traffic rather than by the
 // length of one wavefront's row pipeline (4097^2 and above at six
@@ -1201,6 +1301,17 @@ void launch_restrict2d(int mc, const T *fine, T *coarse, hipStream_t st)
     const long long waves = strips * ((mc + chunk - 1) / chunk);
     const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
     hipLaunchKernelGGL((k_restrict2d<T>), grid, block, 0, st, fine, coarse, mc, chunk);
+}
+
+template <typename T>
+void launch_restrict2d2(int mc, const T *fine, T *coarse, T *coarse2, hipStream_t st)
+{
+    const long long strips = (mc + 61) / 62;
+    int chunk = (int)((mc * strips + 8191) / 8192);
+    chunk = std::max(4, chunk + (chunk & 1));  // even: second-level rows start at even rows
+    const long long waves = strips * ((mc + chunk - 1) / chunk);
+    const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
+    hipLaunchKernelGGL((k_restrict2d2<T>), grid, block, 0, st, fine, coarse, coarse2, mc, chunk);
 }
 
 template <typename T>

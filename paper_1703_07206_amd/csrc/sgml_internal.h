@@ -233,9 +233,11 @@ void launch_boundary(const Variant &v, const Level &L, const T *e, double escale
                      unsigned long long *norm, hipStream_t st);
 
 // wscale: the source is W^-1 f, W the trapezoid weights (1/2 per Neumann
-// face a node lies on), as the transposed solve needs.
+// face a node lies on), as the transposed solve needs.  s32 (or null): the
+// source also in FP32, unscaled (the mixed cycle's source when it needs no
+// scaling).
 void launch_init(const Variant &v, const Level &L, const double *f, const double *G,
-                 const double *sigma, double *s, double *u, unsigned long long *norm0,
+                 const double *sigma, double *s, double *u, float *s32, unsigned long long *norm0,
                  bool wscale, hipStream_t st);
 // u = W u at every node.
 void launch_trap_scale(const Level &L, int dim, double *u, hipStream_t st);

@@ -663,13 +663,14 @@ __device__ __forceinline__ double trap_weight(int i, int j, int k, int m, unsign
     return w;
 }
 
-// Start of a solve: u = 0, s = f at unknowns (0 at Dirichlet nodes), and
-// norm0 = max |f - dL_1 u_init| with u_init = G on Dirichlet nodes, 0 else.
-// WS: the source is W^-1 f (first step of the transposed solve).
+// Start of a solve: u = 0, s = f at unknowns (0 at Dirichlet nodes), s32
+// (if not null) = s in FP32, and norm0 = max |f - dL_1 u_init| with u_init =
+// G on Dirichlet nodes, 0 else.  WS: the source is W^-1 f (first step of the
+// transposed solve).
 template <int DIM, int RAD, int SIG, bool WS>
 __global__ __launch_bounds__(256) void k_init(const double *__restrict__ f, const double *__restrict__ G,
                                               const double *__restrict__ sigma, double *__restrict__ s,
-                                              double *__restrict__ u, Level L,
+                                              double *__restrict__ u, float *__restrict__ s32, Level L,
                                               unsigned long long *__restrict__ norm0)
 {
     int i, j, k;
@@ -680,6 +681,7 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ f, cons
         u[c] = 0.0;
         if (is_dir<DIM>(i, j, k, m, L.dir)) {
             s[c] = 0.0;
+            if (s32) s32[c] = 0.0f;
         } else {
             auto val = [&](int a, int b, int d) -> double {
                 return (G && is_dir<DIM>(a, b, d, m, L.dir)) ? G[lin(a, b, d, m)] : 0.0;
@@ -687,6 +689,7 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ f, cons
             const double Lb = stencil_full<DIM, RAD, SIG>(val, sigma, i, j, k, m, L.dir, L.scale, L.a);
             const double fc = WS ? f[c] / trap_weight<DIM>(i, j, k, m, L.dir) : f[c];
             s[c] = fc;
+            if (s32) s32[c] = (float)fc;
             rb = dbits(fc - Lb);
         }
     }
@@ -1143,14 +1146,14 @@ struct BoundaryRun {
 template <int D, int R, int S>
 struct InitRun {
     static void run(const Level &L, const double *f, const double *G, const double *sigma, double *s,
-                    double *u, unsigned long long *norm0, bool wscale, hipStream_t st)
+                    double *u, float *s32, unsigned long long *norm0, bool wscale, hipStream_t st)
     {
         if (wscale)
             hipLaunchKernelGGL((k_init<D, R, S, true>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, s, u,
-                               L, norm0);
+                               s32, L, norm0);
         else
             hipLaunchKernelGGL((k_init<D, R, S, false>), grid_of(D, L.m), block_of(), 0, st, f, G, sigma, s,
-                               u, L, norm0);
+                               u, s32, L, norm0);
     }
 };
 template <int D, int R, int S>
@@ -1174,9 +1177,9 @@ void launch_boundary(const Variant &v, const Level &L, const T *e, double escale
 }
 
 void launch_init(const Variant &v, const Level &L, const double *f, const double *G, const double *sigma,
-                 double *s, double *u, unsigned long long *norm0, bool wscale, hipStream_t st)
+                 double *s, double *u, float *s32, unsigned long long *norm0, bool wscale, hipStream_t st)
 {
-    dispatch3<InitRun>(v, L, f, G, sigma, s, u, norm0, wscale, st);
+    dispatch3<InitRun>(v, L, f, G, sigma, s, u, s32, norm0, wscale, st);
 }
 
 void launch_trap_scale(const Level &L, int dim, double *u, hipStream_t st)

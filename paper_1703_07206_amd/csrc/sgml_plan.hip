@@ -871,10 +871,12 @@ struct Solve {
         P->prof_untimed = 0;
         SGML_HIP(hipEventRecord(P->ev0, st));
         clear_targets(P, 1, 1, st);
-        launch_init(P->var, L0, f, G, P->sigma, s, u, target(P, 1), wscale, st);
+        // pure Neumann: the source is projected below, its FP32 copy taken after
+        pure = P->dir == 0;
+        float *s32 = mixed && !pure ? reinterpret_cast<float *>(shat) : nullptr;
+        launch_init(P->var, L0, f, G, P->sigma, s, u, s32, target(P, 1), wscale, st);
         // pure Neumann (Sec. 2, last paragraph; eq. (10)): the source minus its
         // trapezoid mean; norm0 is that of the projected source
-        pure = P->dir == 0;
         part = P->at<double>(P->lay.part);
         means = P->at<double>(P->lay.means);
         if (pure) {
@@ -924,7 +926,8 @@ struct Solve {
         // the normal range; within [2^-40, 2^40] no scaling is needed
         const int kn = mixed ? std::ilogb(norm0) : 0;
         k0 = (kn < -40 || kn > 40) ? kn : 0;
-        if (mixed) launch_source_cast<T>(L0, P->dim, s, shat, std::ldexp(1.0, -k0), st);
+        // the FP32 source, unless the initialisation wrote it (unscaled)
+        if (mixed && (k0 != 0 || pure)) launch_source_cast<T>(L0, P->dim, s, shat, std::ldexp(1.0, -k0), st);
         if (g1) launch_restrict<T, T>(P->dim, P->m(1), src0, g1, st);  // cycle 0's level-1 source
         i = 0;
         done = o->max_cycles < 1;

@@ -1173,8 +1173,10 @@ constexpr long long kLargeLevelRows = 1 << 17;
 // half of them in FP64 and in the fused closing visit, whose registers allow
 // two wavefronts per SIMD (152 rows, one wavefront per SIMD).  Measured on
 // the 4097^2 solves: the FP64 and mixed solves 1% faster with half the slots,
-// the FP32 visit 1% slower (unfused mixed solve); a third or a quarter of the
-// slots leaves SIMDs idle (mixed solve +13%, +24%).
+// the FP32 visit 1% slower (unfused mixed solve).  Every SIMD must get the
+// same whole number of wavefronts: 3/8 or 5/8 of the slots (some SIMDs with
+// one more than others, or none) made the mixed solve 8% / 15% slower, a
+// third or a quarter 13% / 24%.
 int chunk_rows(int requested, int m, int strips, int sweeps, long long slots)
 {
     if (requested > 0) return requested;

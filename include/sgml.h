@@ -120,7 +120,7 @@ typedef struct {
                          at most 257; for long
                          visits of large levels the shortest chunk that fills the
                          device's wavefront slots for the kernel in one round, half
-                         of them in FP64 and in the fused closing visit; 96 for the
+                         of them in FP64 and in the fused closing visit; 136 for the
                          cycle
                          end, fewer on levels too small to fill the device), values
                          below 8 act as 8, odd values are rounded up to even in the

@@ -1248,8 +1248,8 @@ void launch_rs(const VisitArgs &a, hipStream_t st)
 }  // namespace
 
 
-// The fused closing visit and cycle end: chunks sized like the long visits
-// (one resident round of wavefronts of this kernel).
+// The fused closing visit and cycle end: chunks sized like the long FP64
+// visits (half of this kernel's wavefront slots: one wavefront per SIMD).
 template <typename T, int RAD, int S>
 long long visit_end_resident_waves()
 {

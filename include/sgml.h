@@ -115,16 +115,14 @@ typedef struct {
                          the generic relaxation, transfer and cycle-end kernels in
                          2D and 3D); values below 64 act as 64 */
     int chunk_rows;   /* rows each wavefront marches through in the 2D row-marching
-                         passes; 0: chosen per launch (8 for short visits, 4 on
-                         levels of at most 1025 nodes per axis, 2 on levels of
-                         at most 257; for long
-                         visits of large levels the shortest chunk that fills the
-                         device's wavefront slots for the kernel in one round, half
-                         of them in FP64 and in the fused closing visit; 136 for the
-                         cycle
-                         end, fewer on levels too small to fill the device), values
-                         below 8 act as 8, odd values are rounded up to even in the
-                         visits */
+                         passes; 0: chosen per launch (short visits: 8 rows, 4 on
+                         levels of at most 1025 nodes per axis, 2 on levels of at
+                         most 257; long visits of large levels: the shortest chunk
+                         that fills the device's wavefront slots for the kernel in
+                         one round, half of them in FP64 and in the fused closing
+                         visit; the cycle end: 136 rows, fewer on levels too small
+                         to fill the device), values below 8 act as 8, odd values
+                         are rounded up to even in the visits */
     int z_chunk;      /* planes each workgroup marches through in the 3D z-marching
                          passes (relaxation, paired relaxation, interpolation,
                          restriction, constant-coefficient cycle end) on levels of

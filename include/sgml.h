@@ -120,9 +120,10 @@ typedef struct {
                          most 257; long visits of large levels: the shortest chunk
                          that fills the device's wavefront slots for the kernel in
                          one round, half of them in FP64 and in the fused closing
-                         visit; the cycle end: 136 rows, fewer on levels too small
-                         to fill the device), values below 8 act as 8, odd values
-                         are rounded up to even in the visits */
+                         visit; the cycle end: two wavefronts per SIMD, 137 rows
+                         on 4097^2, fewer on levels too small to fill the device),
+                         values below 8 act as 8, odd values are rounded up to even
+                         in the visits */
     int z_chunk;      /* planes each workgroup marches through in the 3D z-marching
                          passes (relaxation, paired relaxation, interpolation,
                          restriction, constant-coefficient cycle end) on levels of

@@ -1324,13 +1324,21 @@ void launch_cycle_end2d(const Variant &v, const CycleEndArgs &a0, hipStream_t st
     const bool res = a.g1 != nullptr && a.s_out != nullptr && a.s_out != a.s;
     const int W = res ? 60 : 62;
     const long long strips = (m + W - 1) / W;
-    // 136 rows per wavefront, about two wavefronts per SIMD on 4097^2 (FP64
-    // solve 0.5% faster than with 92 or 96 rows, 3% faster than with 192);
-    // a level too small to give the chip's 1024 SIMDs a wavefront each at 136
-    // rows takes shorter chunks (129^2: 8 rows, 51 wavefronts instead of 3)
-    a.chunk = a0.chunk > 0 ? a0.chunk : 136;
-    if (a0.chunk <= 0 && strips * ((m + 135) / 136) < 1024)
+    // Two wavefronts per SIMD and no SIMD with a third (at most twice as many
+    // wavefronts as SIMDs): on 4097^2 137 rows in FP64 (2010 wavefronts), the
+    // FP64 solve 0.5% faster than with 136 rows (2077: a third wavefront on
+    // some SIMDs), 1% faster than with 92 or 96 (about three per SIMD), 3%
+    // faster than with 192.  A level too small to give the chip's 1024 SIMDs
+    // a wavefront each at 96 rows takes shorter chunks (129^2: 8 rows, 51
+    // wavefronts).
+    if (a0.chunk > 0) {
+        a.chunk = a0.chunk;
+    } else if (strips * ((m + 95) / 96) < 1024) {
         a.chunk = std::max(8, (int)(((long long)m * strips + 1023) / 1024));
+    } else {
+        const long long per = std::max(1LL, 8LL * device_cus() / strips);  // chunks per strip
+        a.chunk = (int)((m + per - 1) / per);
+    }
     if (res) a.chunk = (a.chunk + 1) & ~1;  // chunks start at even rows
     const long long waves = strips * ((m + a.chunk - 1) / a.chunk);
     const dim3 grid((unsigned)((waves + kVisitBlock / 64 - 1) / (kVisitBlock / 64))), block(kVisitBlock);
